@@ -1,0 +1,346 @@
+"""TDA-risp in plain FP64 (oracle; test infrastructure only, never imported by the HIP path).
+
+The matrix of eq. TDA-risp, with the XC kernel dropped, the RI approximation of
+eq. TDDFT-axs_approx_integral, the minimal auxiliary basis of eq. gr without hydrogen functions,
+the exchange-space energy window (section on exchange-space truncation) and the range-separated
+exchange operator J^ = (alpha + beta erf(omega r))/r of eq. RSH / eq. K_mia_RSH:
+
+  A_{ia,jb} = (e_a - e_i) d_ij d_ab + 2 sum_P B^P_ia B^P_jb
+              - [i,j in occK' and a,b in virK'] sum_P Bx^P_ij Bx^P_ab
+
+* B^P_pq = sum_Q (pq|Q) (L^-T)_QP with (P|Q) = L L^T over the Coulomb auxiliary basis (s + p on every
+  non-hydrogen atom). Then sum_P B_ia B_jb = sum_PQ (ia|P)(P|Q)^-1(Q|jb), the RI integral. The paper
+  writes the exchange factors as T_ij = (ij|Q)(Q|P)^-1 and T_ab = (ab|P); the symmetric Cholesky split
+  used here gives the same product and is unique, so factors can be compared element by element.
+* Bx: the same construction over the exchange auxiliary basis (one s function per non-hydrogen atom)
+  with the operator J^ in both the three-centre integrals and the metric ("combined" reading: one RI
+  in the J^ metric, as in eq. K_mia_RSH). For a global hybrid beta = 0 and J^ = c_x/r, so the exchange
+  block equals c_x (ij|ab)_RI. The "split" reading stacks sqrt(alpha) RI(1/r) and sqrt(beta) RI(erf)
+  along P, each in its own metric.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import integrals as I
+
+HARTREE_TO_EV = 27.211386245988  # CODATA 2018
+
+
+@dataclass
+class Params:
+    c_x: float = 0.22  # alpha: full-range exact-exchange fraction
+    beta: float = 0.78  # long-range erf part (omegaB97X-family: alpha + beta = 1)
+    omega: float = 0.2  # bohr^-1
+    window_ev: float = 40.0
+    window_mode: str = "absolute"  # or "frontier"
+    rsh_mode: str = "combined"  # or "split"
+    theta: float = 0.2
+    h_in_aux: bool = False
+    schwarz_tau: float = 1e-10
+
+
+# ----------------------------------------------------------------------------------------------
+# Auxiliary basis (eq. gr; hydrogen omitted; Coulomb: s+p, exchange: s)
+# ----------------------------------------------------------------------------------------------
+def select_aux(Z, aux_radius, theta=0.2, h_in_aux=False):
+    """Auxiliary shells [(atom, l, exponent, 1.0)] for the Coulomb (s and p) and exchange (s) terms.
+
+    One uncontracted primitive per shell with exponent theta / R_A^2 (eq. gr). Atoms with Z == 1 get
+    no auxiliary functions unless h_in_aux. Coulomb order: per atom s then p; exchange: s per atom.
+    """
+    J, K = [], []
+    for a, z in enumerate(Z):
+        if z == 1 and not h_in_aux:
+            continue
+        e = theta / float(aux_radius[a]) ** 2
+        J.append((a, 0, e, 1.0))
+        J.append((a, 1, e, 1.0))
+        K.append((a, 0, e, 1.0))
+    return J, K
+
+
+# ----------------------------------------------------------------------------------------------
+# Energy window (section on exchange-space truncation)
+# ----------------------------------------------------------------------------------------------
+def window_sets(mo_energy, nocc, window_ev=40.0, mode="absolute"):
+    """Occupied and virtual orbitals kept in the exchange term, ascending, 0-based within each space.
+
+    absolute: keep occupied i with e_i * H2EV > -window and virtual a with e_a * H2EV < window.
+    frontier: keep i with (e_LUMO - e_i) * H2EV < window and a with (e_a - e_HOMO) * H2EV < window.
+    """
+    e = np.asarray(mo_energy, dtype=np.float64)
+    eo, ev = e[:nocc], e[nocc:]
+    if mode == "absolute":
+        occ = np.nonzero(eo * HARTREE_TO_EV > -window_ev)[0]
+        vir = np.nonzero(ev * HARTREE_TO_EV < window_ev)[0]
+    elif mode == "frontier":
+        occ = np.nonzero((ev[0] - eo) * HARTREE_TO_EV < window_ev)[0]
+        vir = np.nonzero((ev - eo[-1]) * HARTREE_TO_EV < window_ev)[0]
+    else:
+        raise ValueError(mode)
+    return occ.astype(np.int32), vir.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------------------------
+# Shell-pair screening (Schwarz)
+# ----------------------------------------------------------------------------------------------
+def schwarz_pairs(coords, shells, aux_shells, tau):
+    """Kept shell pairs (A >= B) with Q_AB * Q_aux >= tau, sorted by (A, B); plus the ratio array.
+
+    Q_AB = max sqrt((mu nu|mu nu)) over the functions of the two shells and Q_aux = max_P sqrt((P|P))
+    over the given auxiliary functions. tau = 0 keeps every pair.
+    Returns (pairs [npair, 2] int32, mask [nsh, nsh] bool (symmetric), ratio Q_AB Q_aux / tau or None).
+    """
+    Qab = I.schwarz_diag(coords, shells)
+    Vaux = I.int2c(coords, aux_shells)
+    qaux = float(np.sqrt(np.max(np.diag(Vaux))))
+    nsh = len(shells)
+    A, B = np.tril_indices(nsh)
+    vals = Qab[A, B] * qaux
+    keep = vals >= tau
+    pairs = np.stack([A[keep], B[keep]], axis=1).astype(np.int32)
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    pairs = pairs[order]
+    mask = np.zeros((nsh, nsh), dtype=bool)
+    mask[pairs[:, 0], pairs[:, 1]] = True
+    mask[pairs[:, 1], pairs[:, 0]] = True
+    ratio = vals / tau if tau > 0 else None
+    return pairs, mask, ratio
+
+
+# ----------------------------------------------------------------------------------------------
+# RI factors
+# ----------------------------------------------------------------------------------------------
+def _operator_int3c(coords, shells, aux, alpha, beta, omega, mask, aux_idx=None):
+    """(mu nu| alpha/r + beta erf(omega r)/r |P)."""
+    out = 0.0
+    if alpha != 0.0:
+        out = alpha * I.int3c(coords, shells, aux, None, mask, aux_idx)
+    if beta != 0.0:
+        out = out + beta * I.int3c(coords, shells, aux, omega, mask, aux_idx)
+    return out
+
+
+def _operator_int2c(coords, aux, alpha, beta, omega):
+    out = 0.0
+    if alpha != 0.0:
+        out = alpha * I.int2c(coords, aux)
+    if beta != 0.0:
+        out = out + beta * I.int2c(coords, aux, omega)
+    return out
+
+
+def cholesky_split(V3_mo, V2):
+    """B[P, ...] with sum_P B^P_pq B^P_rs = (pq|P)(P|Q)^-1(Q|rs): B = L^-1 (Q|pq), (P|Q) = L L^T."""
+    L = np.linalg.cholesky(V2)
+    shp = V3_mo.shape
+    Bflat = sla.solve_triangular(L, V3_mo.reshape(shp[0], -1), lower=True)
+    return Bflat.reshape(shp), L
+
+
+@dataclass
+class Factors:
+    nocc: int
+    nvir: int
+    de: np.ndarray  # [nocc, nvir] e_a - e_i
+    B_ia: np.ndarray  # [naux_J, nocc, nvir]
+    Bx_ij: np.ndarray  # [nKaux, noK, noK]
+    Bx_ab: np.ndarray  # [nKaux, nvK, nvK]
+    occK: np.ndarray
+    virK: np.ndarray
+    L_J: np.ndarray = field(repr=False, default=None)
+    L_K: np.ndarray = field(repr=False, default=None)
+    pairs: np.ndarray = field(repr=False, default=None)
+
+
+def build_factors(mol, prm: Params = Params(), pair_mask=None) -> Factors:
+    """All RI factors of the TDA-risp matrix for a synth.Molecule-like object."""
+    coords = mol.coords
+    shells = mol.shells
+    auxJ, auxK = select_aux(mol.Z, mol.aux_radius, prm.theta, prm.h_in_aux)
+    if pair_mask is None:
+        pairs, pair_mask, _ = schwarz_pairs(coords, shells, auxJ, prm.schwarz_tau)
+    else:
+        pairs = None
+    C = mol.mo_coeff
+    nocc = mol.nocc
+    Co, Cv = C[:, :nocc], C[:, nocc:]
+    occK, virK = window_sets(mol.mo_energy, nocc, prm.window_ev, prm.window_mode)
+    CoK, CvK = Co[:, occK], Cv[:, virK]
+    # Coulomb factor
+    V3 = I.int3c(coords, shells, auxJ, None, pair_mask)  # [nao, nao, naux]
+    Tia = np.einsum("mi,mnP,na->Pia", Co, V3, Cv, optimize=True)
+    B_ia, L_J = cholesky_split(Tia, I.int2c(coords, auxJ))
+    del V3
+    # exchange factors in the J^ metric
+    Bx_ij, Bx_ab, L_K = _exchange_factors(coords, shells, auxK, prm, pair_mask, CoK, CvK)
+    e = mol.mo_energy
+    de = e[None, nocc:] - e[:nocc, None]
+    return Factors(nocc=nocc, nvir=C.shape[1] - nocc, de=de, B_ia=B_ia, Bx_ij=Bx_ij, Bx_ab=Bx_ab,
+                   occK=occK, virK=virK, L_J=L_J, L_K=L_K, pairs=pairs)
+
+
+def _exchange_factors(coords, shells, auxK, prm, pair_mask, CoK, CvK):
+    def one(alpha, beta):
+        V3 = _operator_int3c(coords, shells, auxK, alpha, beta, prm.omega, pair_mask)
+        V2 = _operator_int2c(coords, auxK, alpha, beta, prm.omega)
+        Tij = np.einsum("mi,mnP,nj->Pij", CoK, V3, CoK, optimize=True)
+        Tab = np.einsum("ma,mnP,nb->Pab", CvK, V3, CvK, optimize=True)
+        L = np.linalg.cholesky(V2)
+        nK = V2.shape[0]
+        Bij = sla.solve_triangular(L, Tij.reshape(nK, -1), lower=True).reshape(Tij.shape)
+        Bab = sla.solve_triangular(L, Tab.reshape(nK, -1), lower=True).reshape(Tab.shape)
+        return Bij, Bab, L
+
+    noK, nvK = CoK.shape[1], CvK.shape[1]
+    if prm.c_x == 0.0 and prm.beta == 0.0:
+        return np.zeros((0, noK, noK)), np.zeros((0, nvK, nvK)), None
+    if prm.rsh_mode == "combined":
+        return one(prm.c_x, prm.beta)
+    if prm.rsh_mode == "split":
+        parts = []
+        if prm.c_x != 0.0:
+            parts.append(one(prm.c_x, 0.0))
+        if prm.beta != 0.0:
+            parts.append(one(0.0, prm.beta))
+        Bij = np.concatenate([p[0] for p in parts])
+        Bab = np.concatenate([p[1] for p in parts])
+        return Bij, Bab, None
+    raise ValueError(prm.rsh_mode)
+
+
+# ----------------------------------------------------------------------------------------------
+# The matrix and its product with trial vectors
+# ----------------------------------------------------------------------------------------------
+def dense_A(F: Factors) -> np.ndarray:
+    """A [nocc*nvir, nocc*nvir], row index i*nvir + a."""
+    o, v = F.nocc, F.nvir
+    Bf = F.B_ia.reshape(F.B_ia.shape[0], o * v)
+    A = 2.0 * Bf.T @ Bf
+    A[np.diag_indices(o * v)] += F.de.ravel()
+    if F.Bx_ij.shape[0]:
+        K = np.einsum("Pij,Pab->iajb", F.Bx_ij, F.Bx_ab, optimize=True)
+        A4 = A.reshape(o, v, o, v)
+        ix = np.ix_(F.occK, F.virK, F.occK, F.virK)
+        A4[ix] -= K
+    return A
+
+
+def sigma(F: Factors, X: np.ndarray) -> np.ndarray:
+    """sigma = A X for a block X [m][nocc][nvir], matrix-free.
+
+    sigma = de*X + 2 sum_P B^P_ia (sum_jb B^P_jb X_mjb) - scatter_window(K), where the exchange part
+    K_mia = sum_P sum_jb Bx^P_ij Bx^P_ab X_mjb runs over the window only.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    m = X.shape[0]
+    o, v = F.nocc, F.nvir
+    out = F.de[None] * X
+    Bf = F.B_ia.reshape(F.B_ia.shape[0], o * v)
+    Y = Bf @ X.reshape(m, o * v).T  # [P, m]
+    out += 2.0 * (Y.T @ Bf).reshape(m, o, v)
+    if F.Bx_ij.shape[0]:
+        Xw = X[:, F.occK][:, :, F.virK]  # [m, noK, nvK]
+        K = np.zeros_like(Xw)
+        for P in range(F.Bx_ij.shape[0]):
+            M = Xw @ F.Bx_ab[P]  # M^P_mja = sum_b Xw_mjb Bx^P_ba (Bx^P_ab is symmetric in a, b)
+            K += np.einsum("ij,mja->mia", F.Bx_ij[P], M)
+        out[np.ix_(np.arange(m), F.occK, F.virK)] -= K
+    return out
+
+
+def lowest_eigh(A, n):
+    w, U = np.linalg.eigh(A)
+    return w[:n], U[:, :n].T
+
+
+# ----------------------------------------------------------------------------------------------
+# Block Davidson (section on large-system Davidson diagonalisation)
+# ----------------------------------------------------------------------------------------------
+@dataclass
+class DavidsonResult:
+    energies: np.ndarray
+    vectors: np.ndarray  # [nstates, nocc*nvir]
+    iters: int
+    restarts: int
+    nsigma: int
+    converged: bool
+    resid: list
+
+
+def davidson(F: Factors, nstates, tol=1e-6, block=None, max_space=None, max_iter=200, sigma_fn=None):
+    """Block Davidson for the lowest eigenpairs of A (FP64).
+
+    Guess: unit vectors at the lowest e_a - e_i (ties by (i, a)). Each iteration: Rayleigh-Ritz on
+    the subspace, residuals r_k = A x_k - theta_k x_k for the lowest `block` Ritz pairs, corrections
+    t_k = r_k / (theta_k - de) (|theta - de| floored at 1e-8), two-pass classical Gram-Schmidt
+    against the subspace, drop vectors whose norm falls below 1e-6. Converged when ||r_k|| < tol for
+    k < nstates. When the subspace would exceed max_space, restart from the current Ritz vectors and
+    recompute their products A V.
+    """
+    o, v = F.nocc, F.nvir
+    n = o * v
+    if block is None:
+        block = min(2 * nstates, 30)
+    block = min(block, n)
+    if max_space is None:
+        max_space = max(8 * block, nstates + 2 * block)
+    sig = sigma_fn or (lambda X: sigma(F, X.reshape(-1, o, v)).reshape(-1, n))
+    d = F.de.ravel()
+    order = np.lexsort((np.arange(n), d))[:block]  # stable: ties keep (i, a) order
+    V = np.zeros((block, n))
+    V[np.arange(block), order] = 1.0
+    W = sig(V)
+    nsig = block
+    restarts = 0
+    resid = []
+    for it in range(1, max_iter + 1):
+        H = V @ W.T
+        H = 0.5 * (H + H.T)
+        theta, y = np.linalg.eigh(H)
+        k = min(block, len(theta))
+        theta, y = theta[:k], y[:, :k]
+        Xr = y.T @ V
+        R = y.T @ W - theta[:, None] * Xr
+        rn = np.linalg.norm(R, axis=1)
+        resid.append(rn[:nstates].copy())
+        if np.all(rn[:nstates] < tol):
+            return DavidsonResult(theta[:nstates], Xr[:nstates], it, restarts, nsig, True, resid)
+        todo = [j for j in range(k) if rn[j] >= tol]
+        den = theta[todo, None] - d[None, :]
+        den = np.where(np.abs(den) < 1e-8, np.where(den < 0, -1e-8, 1e-8), den)
+        T = R[todo] / den
+        T = T / np.linalg.norm(T, axis=1, keepdims=True)  # drop test below is relative to unit length
+        if V.shape[0] + T.shape[0] > max_space:
+            # restart: keep the Ritz vectors, recompute A V for consistency
+            V = Xr
+            W = sig(V)
+            nsig += V.shape[0]
+            restarts += 1
+        for _ in range(2):
+            T = T - (T @ V.T) @ V
+        keep = []
+        for j in range(T.shape[0]):
+            t = T[j]
+            for q in keep:
+                t = t - np.dot(T[q], t) * T[q]
+            t = t - (t @ V.T) @ V
+            nt = np.linalg.norm(t)
+            if nt > 1e-6:
+                T[j] = t / nt
+                keep.append(j)
+        T = T[keep]
+        if T.shape[0] == 0:
+            break
+        WT = sig(T)
+        nsig += T.shape[0]
+        V = np.vstack([V, T])
+        W = np.vstack([W, WT])
+    H = V @ W.T
+    theta, y = np.linalg.eigh(0.5 * (H + H.T))
+    return DavidsonResult(theta[:nstates], (y[:, :nstates].T @ V), max_iter, restarts, nsig, False, resid)

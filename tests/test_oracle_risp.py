@@ -1,0 +1,231 @@
+"""Pins of the oracle's TDA-risp matrix, factors, product and eigensolvers.
+
+The brute-force reference assembles A element by element from 4-index AO integrals built with the
+explicit inverse of the metric, (mu nu|P)(P|Q)^-1(Q|kappa lambda), transformed to the MO basis by a
+separate 4-index contraction, with the window applied by explicit membership tests (eq. TDA-risp,
+eq. TDDFT-axs_approx_integral, eq. K_mia_RSH and the exchange-space window).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrals as I
+from oracle import risp as R
+
+H2EV = 27.211386245988
+
+
+def tiny_molecule(seed=7):
+    """3 C + 2 H, a few bohr apart; nao = 37, nocc = 7, nvir = 30."""
+    rng = np.random.default_rng(seed)
+    C = np.array([[0.0, 0.0, 0.0], [1.42, 0.1, -0.05], [2.1, 1.25, 0.2]]) + rng.uniform(-0.1, 0.1, (3, 3))
+    H = np.array([[-0.6, -0.9, 0.3], [2.9, 1.6, -0.7]])
+    ss = np.random.SeedSequence(seed).spawn(2)
+    return synth.make_system(C, H, np.random.default_rng(ss[0]), np.random.default_rng(ss[1]), seed, "tiny5")
+
+
+def brute_A(mol, prm):
+    auxJ, auxK = R.select_aux(mol.Z, mol.aux_radius, prm.theta, prm.h_in_aux)
+    C = mol.mo_coeff
+    o = mol.nocc
+    v = C.shape[1] - o
+    e = mol.mo_energy
+    # Coulomb: (mu nu|k l)_RI with the explicit inverse
+    V3 = I.int3c(mol.coords, mol.shells, auxJ)
+    Vinv = np.linalg.inv(I.int2c(mol.coords, auxJ))
+    ao4 = np.einsum("mnP,PQ,klQ->mnkl", V3, Vinv, V3, optimize=True)
+    mo4 = np.einsum("mnkl,mp,nq,kr,ls->pqrs", ao4, C, C, C, C, optimize=True)
+    # exchange operator J^ = c_x/r + beta erf(omega r)/r, one RI in its own metric
+    V3x = prm.c_x * I.int3c(mol.coords, mol.shells, auxK) + prm.beta * I.int3c(mol.coords, mol.shells, auxK, prm.omega)
+    V2x = prm.c_x * I.int2c(mol.coords, auxK) + prm.beta * I.int2c(mol.coords, auxK, prm.omega)
+    ao4x = np.einsum("mnP,PQ,klQ->mnkl", V3x, np.linalg.inv(V2x), V3x, optimize=True)
+    mo4x = np.einsum("mnkl,mp,nq,kr,ls->pqrs", ao4x, C, C, C, C, optimize=True)
+    occK, virK = R.window_sets(e, o, prm.window_ev, prm.window_mode)
+    occK, virK = set(occK.tolist()), set(virK.tolist())
+    A = np.zeros((o * v, o * v))
+    for i in range(o):
+        for a in range(v):
+            for j in range(o):
+                for b in range(v):
+                    val = 2.0 * mo4[i, o + a, j, o + b]
+                    if i == j and a == b:
+                        val += e[o + a] - e[i]
+                    if i in occK and j in occK and a in virK and b in virK:
+                        val -= mo4x[i, j, o + a, o + b]
+                    A[i * v + a, j * v + b] = val
+    return A
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return tiny_molecule()
+
+
+@pytest.mark.parametrize("window", [40.0, 25.0])
+def test_dense_A_matches_brute_force(tiny, window):
+    prm = R.Params(window_ev=window, schwarz_tau=0.0)
+    F = R.build_factors(tiny, prm)
+    A = R.dense_A(F)
+    Ab = brute_A(tiny, prm)
+    assert np.abs(A - Ab).max() <= 1e-12 * np.abs(Ab).max()
+    if window == 25.0:  # the window must actually cut something in this case
+        assert len(F.virK) < F.nvir
+
+
+def test_A_symmetric_and_coulomb_psd(tiny):
+    F = R.build_factors(tiny, R.Params(schwarz_tau=0.0))
+    A = R.dense_A(F)
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    Bf = F.B_ia.reshape(F.B_ia.shape[0], -1)
+    J = 2.0 * Bf.T @ Bf
+    lam = np.linalg.eigvalsh(J)
+    assert lam.min() >= -1e-12 * lam.max()
+
+
+def test_factor_split_equals_explicit_inverse(tiny):
+    auxJ, _ = R.select_aux(tiny.Z, tiny.aux_radius)
+    V3 = I.int3c(tiny.coords, tiny.shells, auxJ)
+    V2 = I.int2c(tiny.coords, auxJ)
+    B, L = R.cholesky_split(V3.transpose(2, 0, 1).copy(), V2)
+    assert np.abs(L @ L.T - V2).max() <= 1e-14 * np.abs(V2).max()
+    lhs = np.einsum("Pmn,Pkl->mnkl", B, B)
+    rhs = np.einsum("mnP,PQ,klQ->mnkl", V3, np.linalg.inv(V2), V3)
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+def test_window_infinite_equals_untruncated_and_zero_removes_exchange(tiny):
+    o = tiny.nocc
+    full = R.dense_A(R.build_factors(tiny, R.Params(window_ev=1e9, schwarz_tau=0.0)))
+    # untruncated exchange coded separately: (ij|ab) over all orbitals
+    F = R.build_factors(tiny, R.Params(window_ev=1e9, schwarz_tau=0.0))
+    assert len(F.occK) == o and len(F.virK) == F.nvir
+    noex = R.dense_A(R.build_factors(tiny, R.Params(c_x=0.0, beta=0.0, schwarz_tau=0.0)))
+    K = np.einsum("Pij,Pab->iajb", F.Bx_ij, F.Bx_ab).reshape(full.shape)
+    assert np.abs((noex - K) - full).max() <= 1e-13 * np.abs(full).max()
+    zero = R.dense_A(R.build_factors(tiny, R.Params(window_ev=0.0, schwarz_tau=0.0)))
+    assert np.abs(zero - noex).max() <= 1e-14 * np.abs(noex).max()
+
+
+def test_no_coulomb_no_exchange_gives_orbital_gaps(tiny):
+    F = R.build_factors(tiny, R.Params(c_x=0.0, beta=0.0, schwarz_tau=0.0))
+    F.B_ia[...] = 0.0
+    w = np.linalg.eigvalsh(R.dense_A(F))
+    assert np.array_equal(w, np.sort(F.de.ravel())) or np.abs(w - np.sort(F.de.ravel())).max() <= 1e-15
+
+
+def test_weyl_bound_without_exchange(tiny):
+    F = R.build_factors(tiny, R.Params(c_x=0.0, beta=0.0, schwarz_tau=0.0))
+    w = np.linalg.eigvalsh(R.dense_A(F))
+    d = np.sort(F.de.ravel())
+    assert np.all(w >= d - 1e-13)
+
+
+def test_energies_translation_and_aux_scaling_invariant(tiny):
+    prm = R.Params(schwarz_tau=0.0)
+    w0 = np.linalg.eigvalsh(R.dense_A(R.build_factors(tiny, prm)))[:6]
+    shifted = tiny_molecule()
+    shifted.coords = shifted.coords + np.array([2.0, -1.0, 0.5])
+    w1 = np.linalg.eigvalsh(R.dense_A(R.build_factors(shifted, prm)))[:6]
+    assert np.abs(w0 - w1).max() <= 1e-12
+    # RI is invariant under a nonsingular rescaling of the auxiliary functions
+    orig = R.select_aux
+
+    def scaled(Z, rad, theta=0.2, h=False):
+        J, K = orig(Z, rad, theta, h)
+        return ([(a, l, e, 1.7 + 0.1 * k) for k, (a, l, e, _) in enumerate(J)],
+                [(a, l, e, 0.6 + 0.2 * k) for k, (a, l, e, _) in enumerate(K)])
+
+    R.select_aux = scaled
+    try:
+        w2 = np.linalg.eigvalsh(R.dense_A(R.build_factors(tiny, prm)))[:6]
+    finally:
+        R.select_aux = orig
+    assert np.abs(w0 - w2).max() <= 1e-12
+
+
+def test_rsh_split_equals_combined_when_beta_zero_or_omega_large(tiny):
+    for kw in (dict(beta=0.0), dict(omega=1e6)):
+        a = R.dense_A(R.build_factors(tiny, R.Params(rsh_mode="combined", schwarz_tau=0.0, **kw)))
+        b = R.dense_A(R.build_factors(tiny, R.Params(rsh_mode="split", schwarz_tau=0.0, **kw)))
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
+    a = R.dense_A(R.build_factors(tiny, R.Params(rsh_mode="combined", schwarz_tau=0.0)))
+    b = R.dense_A(R.build_factors(tiny, R.Params(rsh_mode="split", schwarz_tau=0.0)))
+    assert np.abs(a - b).max() > 1e-8  # the two readings differ in general
+
+
+def test_sigma_equals_dense_product(tiny):
+    F = R.build_factors(tiny, R.Params(window_ev=25.0))
+    A = R.dense_A(F)
+    X = synth.random_trial_vectors(5, F.nocc, F.nvir, 3)
+    S = R.sigma(F, X)
+    ref = (A @ X.reshape(5, -1).T).T.reshape(S.shape)
+    assert np.abs(S - ref).max() <= 1e-13 * np.abs(ref).max()
+    # bilinear symmetry and linearity
+    Y = synth.random_trial_vectors(5, F.nocc, F.nvir, 4)
+    assert abs(np.sum(Y * R.sigma(F, X)) - np.sum(X * R.sigma(F, Y))) <= 1e-13
+    assert np.abs(R.sigma(F, 2 * X - Y) - (2 * S - R.sigma(F, Y))).max() <= 1e-13
+
+
+def test_window_sets_by_hand():
+    e = np.array([-2.0, -40.0 / H2EV, -39.0 / H2EV, -0.3, 0.1, 1.0, 40.0 / H2EV, 1.5, 3.0])
+    occ, vir = R.window_sets(e, 4, 40.0)
+    assert occ.tolist() == [2, 3]  # -40 eV exactly is not kept (strict)
+    assert vir.tolist() == [0, 1]  # 40 eV exactly is not kept; 1.5 Ha = 40.8 eV is dropped
+    # frontier: LUMO = 0.1 Ha, HOMO = -0.3 Ha; (0.1 - e_i) eV = 41.7 for i = 2, 10.9 for i = 3;
+    # (e_a + 0.3) eV = 10.9, 35.4, 48.2, 49.0, 89.8
+    occ, vir = R.window_sets(e, 4, 40.0, "frontier")
+    assert occ.tolist() == [3] and vir.tolist() == [0, 1]
+    occ, vir = R.window_sets(e, 4, 1e9)
+    assert occ.tolist() == [0, 1, 2, 3] and vir.tolist() == [0, 1, 2, 3, 4]
+
+
+def test_select_aux_counts():
+    mol = synth.make_config0()
+    J, K = R.select_aux(mol.Z, mol.aux_radius)
+    nC = int(np.sum(mol.Z == 6))
+    assert sum(1 if l == 0 else 3 for (_, l, _, _) in J) == 4 * nC == 48
+    assert len(K) == nC and all(l == 0 for (_, l, _, _) in K)
+    assert all(mol.Z[a] == 6 for (a, _, _, _) in J)
+    e = J[0][2]
+    assert e == pytest.approx(0.2 / (0.76 * synth.ANGSTROM_TO_BOHR) ** 2)
+    J2, K2 = R.select_aux(mol.Z, mol.aux_radius, h_in_aux=True)
+    assert len(K2) == mol.natm
+
+
+def test_screening_limits_and_monotone():
+    mol = tiny_molecule()
+    auxJ, _ = R.select_aux(mol.Z, mol.aux_radius)
+    nsh = len(mol.shells)
+    p0, _, _ = R.schwarz_pairs(mol.coords, mol.shells, auxJ, 0.0)
+    assert len(p0) == nsh * (nsh + 1) // 2
+    prev = None
+    for tau in (1e-12, 1e-6, 1e-3, 1e-1):
+        p, mask, ratio = R.schwarz_pairs(mol.coords, mol.shells, auxJ, tau)
+        s = set(map(tuple, p.tolist()))
+        if prev is not None:
+            assert s <= prev
+        prev = s
+    assert len(prev) < len(p0)
+
+
+def test_davidson_matches_eigh_config0():
+    mol = synth.make_config0()
+    F = R.build_factors(mol, R.Params())
+    w, U = R.lowest_eigh(R.dense_A(F), 5)
+    r = R.davidson(F, 5, tol=1e-7)
+    assert r.converged
+    assert np.abs(r.energies - w).max() <= 1e-10
+    for k in range(5):
+        assert abs(abs(np.dot(r.vectors[k], U[k])) - 1.0) <= 1e-8
+    r2 = R.davidson(F, 5, tol=1e-7, max_space=30)
+    assert r2.converged and r2.restarts > 0
+    assert np.abs(r2.energies - w).max() <= 1e-10
+
+
+def test_screening_changes_energies_negligibly():
+    mol = synth.make_config0()
+    A1 = R.dense_A(R.build_factors(mol, R.Params(schwarz_tau=1e-10)))
+    A0 = R.dense_A(R.build_factors(mol, R.Params(schwarz_tau=0.0)))
+    w1 = np.linalg.eigvalsh(A1)[:5]
+    w0 = np.linalg.eigvalsh(A0)[:5]
+    assert np.abs(w1 - w0).max() <= 1e-8
