@@ -1,0 +1,214 @@
+/*
+ * risp.h - C ABI of the MI355X (gfx950) TDA-risp library (librisp.so).
+ *
+ * The library computes the lowest excitation energies and vectors of the TDA-risp matrix
+ * (Zhou et al., "GPU Accelerated Minimal Auxiliary Basis Approach TDDFT for Large Organic
+ * Molecules", eq. TDA and eq. TDA-risp):
+ *
+ *   A_{ia,jb} = (e_a - e_i) d_ij d_ab + 2 (ia|jb) - (ij|J^|ab)          (exchange only inside the window)
+ *
+ * with the RI approximation of eq. TDDFT-axs_approx_integral over the minimal auxiliary basis of
+ * eq. gr (one primitive s + p per non-hydrogen atom for Coulomb, one s for exchange, hydrogen
+ * omitted), the exchange-space energy window of the section on exchange-space truncation and the
+ * range-separated operator J^ = (alpha + beta erf(omega r))/r of eq. RSH / eq. K_mia_RSH.
+ *
+ * Conventions shared by every entry point:
+ *  - Units: bohr and Hartree. Cartesian p components are ordered x, y, z.
+ *  - Matrices are row-major. Orbital pairs (i, a) are flattened as i * nvir + a.
+ *  - Status: RISP_OK (0) or a negative RISP_E_* code; the message of the last failure on the calling
+ *    thread is returned by risp_last_error(). On failure no output is written. No C++ exception
+ *    crosses the ABI.
+ *  - Inputs are borrowed for the duration of the call only. Outputs go to caller buffers.
+ *  - "dev" pointers are device (HBM) addresses on the context's device; every other pointer is host.
+ *  - Work is ordered on the context stream. Calls that return host results synchronise that stream;
+ *    risp_sigma does not synchronise.
+ *  - A context is used by one thread at a time.
+ */
+#ifndef RISP_H
+#define RISP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t risp_status;
+enum {
+  RISP_OK = 0,
+  RISP_PENDING = 1,
+  RISP_E_ARG = -1,      /* invalid argument (null pointer, bad enum, negative size) */
+  RISP_E_SHAPE = -2,    /* inconsistent sizes (nao vs shells, nocc > nmo, ...) */
+  RISP_E_NOMEM = -3,    /* device allocation failed */
+  RISP_E_HIP = -4,      /* HIP runtime error */
+  RISP_E_NOTCONV = -5,  /* Davidson reached max_iter; results are the last Ritz pairs */
+  RISP_E_STATE = -6,    /* object used with the wrong context or after free */
+  RISP_E_NOTFOUND = -7
+};
+
+/* precision of the stored factors and of the sigma contractions */
+enum { RISP_FP64 = 0, RISP_FP32 = 1, RISP_BF16 = 2 };
+/* reading of the range-separated exchange: one RI in the J^ metric (paper eq. K_mia_RSH) or
+ * alpha RI(1/r) + beta RI(erf) stacked along the auxiliary index */
+enum { RISP_RSH_COMBINED = 0, RISP_RSH_SPLIT = 1 };
+/* window reference: absolute orbital energies (as written in the paper) or distances to the
+ * frontier orbitals */
+enum { RISP_WIN_ABSOLUTE = 0, RISP_WIN_FRONTIER = 1 };
+
+/* One uncontracted primitive Cartesian Gaussian shell: coef * N * x^lx y^ly z^lz exp(-exponent r^2)
+ * centred on `atom`, with N the normalisation of the primitive (l = 0 or 1 only). */
+typedef struct {
+  int32_t atom;
+  int32_t l;
+  double exponent;
+  double coef;
+} risp_shell;
+
+/* The problem as the paper states it: geometry, AO basis, MO coefficients and energies. */
+typedef struct {
+  int32_t natm;
+  const double *coords;     /* [natm][3] bohr */
+  const int32_t *Z;         /* [natm] nuclear charges; Z == 1 marks hydrogen */
+  const double *aux_radius; /* [natm] semi-empirical radius R_A (bohr) of eq. gr */
+  int32_t nshell;
+  const risp_shell *shells; /* AO shells; functions are numbered shell by shell */
+  int32_t nao, nmo, nocc;
+  const double *mo_coeff;   /* [nao][nmo] */
+  const double *mo_energy;  /* [nmo], ascending within occupied and within virtual */
+} risp_system;
+
+typedef struct {
+  double c_x;         /* alpha of J^ (full-range exact-exchange fraction), e.g. 0.22 */
+  double beta;        /* beta of J^ (long-range erf part), e.g. 0.78; 0 for a global hybrid */
+  double omega;       /* range-separation parameter (bohr^-1), e.g. 0.2 */
+  double window_ev;   /* exchange window (eV), e.g. 40 */
+  double theta;       /* auxiliary exponent parameter of eq. gr: exponent = theta / R_A^2 */
+  double schwarz_tau; /* shell-pair screening threshold on Q_AB * max_P sqrt((P|P)); 0 keeps all */
+  int32_t rsh_mode;   /* RISP_RSH_* */
+  int32_t window_mode;/* RISP_WIN_* */
+  int32_t precision;  /* RISP_FP64 / RISP_FP32 / RISP_BF16 */
+  int32_t h_in_aux;   /* 0: hydrogen omitted from both auxiliary bases (paper's production setting) */
+  int32_t bf16_scale; /* BF16 only: 1 stores each auxiliary slice scaled by a power of two */
+  int32_t reserved;
+} risp_params;
+
+typedef struct {
+  int32_t nstates;         /* number of lowest roots */
+  int32_t block;           /* trial vectors per sigma block; 0 = min(2 nstates, 30) */
+  int32_t max_space;       /* subspace size that triggers a restart; 0 = 8 * block */
+  int32_t max_iter;        /* 0 = 200 */
+  double tol;              /* residual 2-norm convergence threshold per state */
+  int32_t correction_pass; /* BF16 factors: refine the BF16-converged vectors with FP32 products */
+  int32_t correction_steps;/* FP32 Davidson steps after the FP32 Rayleigh-Ritz; 0 = 3 */
+  double bf16_tol;         /* BF16 stage stops at max(tol, bf16_tol) or when its residual stalls;
+                              0 = 1e-4 */
+  int32_t nx0;             /* optional initial vectors (resume): count, 0 = unit-vector guess */
+  int32_t reserved;
+  const float *x0;         /* [nx0][nocc*nvir] host */
+} risp_dav_opts;
+
+typedef struct {
+  int32_t iters, restarts, sigma_vectors, converged;
+  int32_t correction_iters, reserved;
+  double t_build, t_sigma, t_subspace, t_correct; /* seconds */
+  double sigma_flops;                              /* algorithmic flops of all sigma blocks */
+  int64_t hbm_bytes;                               /* device bytes held by the factors */
+  double resid_hist[256];                          /* max residual norm per iteration */
+} risp_dav_info;
+
+typedef struct {
+  int32_t nao, nmo, nocc, nvir;
+  int32_t naux_j, naux_k; /* Coulomb and exchange auxiliary functions (naux_k counts both RI
+                             blocks in RISP_RSH_SPLIT) */
+  int32_t nocc_k, nvir_k; /* orbitals inside the exchange window */
+  int32_t npair;          /* shell pairs kept by screening */
+  int32_t precision;
+  int64_t bytes;          /* device bytes held by the factor object */
+  const void *t_ia;       /* dev [naux_j][nocc][nvir] in `precision` (BF16: stored / scale) */
+  const void *t_ij;       /* dev [nocc_k][naux_k][nocc_k] */
+  const void *t_ab;       /* dev [naux_k][nvir_k][nvir_k] */
+  const float *scale_ia;  /* dev [naux_j] power-of-two scales (BF16), else NULL */
+  const float *scale_k;   /* dev [naux_k] product of the T_ij and T_ab scales (BF16), else NULL */
+  const int32_t *occ_k;   /* dev [nocc_k] window occupied indices, ascending */
+  const int32_t *vir_k;   /* dev [nvir_k] window virtual indices (0-based in the virtual space) */
+} risp_factors_desc;
+
+typedef struct risp_ctx risp_ctx;
+typedef struct risp_factors risp_factors;
+
+/* Last error message of the calling thread ("" if none). */
+const char *risp_last_error(void);
+
+/* Create a context on HIP device `device`. hip_stream: a hipStream_t to order work on, or NULL for
+ * a stream owned by the context. */
+risp_status risp_ctx_create(int32_t device, void *hip_stream, risp_ctx **out);
+risp_status risp_ctx_destroy(risp_ctx *ctx);
+
+/* ---- stages of the factor build (exposed for validation; risp_build_factors runs them all) ---- */
+
+/* Auxiliary basis of eq. gr (section on exchange-space truncation for the hydrogen rule): for each
+ * atom with Z > 1 (or every atom when h_in_aux) one s and one p primitive with exponent
+ * theta / R_A^2 for Coulomb, and the s primitive for exchange. Writes up to `cap` shells to each
+ * array (host) and the counts. */
+risp_status risp_select_aux(const risp_system *sys, const risp_params *prm, int32_t cap,
+                            risp_shell *aux_j, int32_t *n_j, risp_shell *aux_k, int32_t *n_k);
+
+/* Exchange window (section on exchange-space truncation): indices of occupied orbitals i with
+ * e_i * 27.211386245988 > -window_ev and of virtual orbitals a (0-based in the virtual space) with
+ * e_a * 27.211386245988 < window_ev (RISP_WIN_ABSOLUTE), computed on the device. occ_k [nocc] and
+ * vir_k [nmo - nocc] are host buffers; counts returned in *nocc_k, *nvir_k. */
+risp_status risp_window(risp_ctx *ctx, int32_t nmo, int32_t nocc, const double *mo_energy,
+                        double window_ev, int32_t window_mode, int32_t *occ_k, int32_t *nocc_k,
+                        int32_t *vir_k, int32_t *nvir_k);
+
+/* Schwarz shell-pair screening on the device: keeps (A >= B) when
+ * max_{mu in A, nu in B} sqrt((mu nu|mu nu)) * max_P sqrt((P|P)) >= tau over the given auxiliary
+ * shells. pairs: host [cap][2] receives the kept pairs in ascending (A, B) order. */
+risp_status risp_screen(risp_ctx *ctx, const risp_system *sys, int32_t naux_shell,
+                        const risp_shell *aux, double tau, int32_t cap, int32_t *pairs,
+                        int32_t *npair);
+
+/* Two-centre integrals (P|Q) (omega <= 0) or (P|erf(omega r)/r|Q) over the auxiliary shells,
+ * FP64 on the device, written to host out [naux][naux]. */
+risp_status risp_int2c(risp_ctx *ctx, const risp_system *sys, int32_t naux_shell,
+                       const risp_shell *aux, double omega, double *out);
+
+/* Three-centre integrals (mu nu|P) (omega <= 0) or with erf(omega r)/r, FP64 Obara-Saika on the
+ * device for the auxiliary shells [aux_begin, aux_end), all AO pairs (tau = 0) or the pairs kept by
+ * screening against `aux` at tau. out: host [naux_sel][nao][nao]. */
+risp_status risp_int3c(risp_ctx *ctx, const risp_system *sys, int32_t naux_shell,
+                       const risp_shell *aux, int32_t aux_begin, int32_t aux_end, double omega,
+                       double tau, double *out);
+
+/* ---- the method ---- */
+
+/* Build every factor of the TDA-risp matrix on the device: auxiliary selection, window, screening,
+ * metric (P|Q) and (P|J^|Q) with FP64 Cholesky, (mu nu|P) and (mu nu|J^|P) integrals, MO transforms
+ * and metric application in FP64, storage in `precision` (section on exchange-space truncation;
+ * eq. TDDFT-axs_approx_integral). */
+risp_status risp_build_factors(risp_ctx *ctx, const risp_system *sys, const risp_params *prm,
+                               risp_factors **out);
+risp_status risp_factors_query(const risp_factors *f, risp_factors_desc *out);
+risp_status risp_factors_free(risp_factors *f);
+
+/* sigma = A X for m trial vectors (eq. TDA-risp with the factors): diagonal term, Coulomb
+ * 2 T_ia (T_jb^T X) and windowed exchange sum_P T_ij^P X T_ab^P. X_dev and sigma_dev are device
+ * [m][nocc][nvir] arrays of doubles (dtype RISP_FP64) or floats (RISP_FP32). Stream-ordered, no
+ * synchronisation. Factors stored in BF16 compute in BF16 with FP32 accumulation and take FP32
+ * X / sigma. */
+risp_status risp_sigma(risp_ctx *ctx, const risp_factors *f, int32_t m, const void *X_dev,
+                       void *sigma_dev, int32_t dtype);
+
+/* Lowest nstates eigenpairs of A by block Davidson (section on large-system Davidson
+ * diagonalisation): sigma blocks on MFMA, FP64 subspace projection, Gram-Schmidt and Jacobi
+ * eigensolver on the device, restart when the subspace reaches max_space. energies: host
+ * [nstates]; vectors: host [nstates][nocc*nvir] or NULL; info may be NULL.
+ * Returns RISP_E_NOTCONV (with the last Ritz pairs written) if max_iter is reached. */
+risp_status risp_davidson(risp_ctx *ctx, const risp_factors *f, const risp_dav_opts *opts,
+                          double *energies, float *vectors, risp_dav_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RISP_H */

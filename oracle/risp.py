@@ -172,11 +172,9 @@ def build_factors(mol, prm: Params = Params(), pair_mask=None) -> Factors:
     Co, Cv = C[:, :nocc], C[:, nocc:]
     occK, virK = window_sets(mol.mo_energy, nocc, prm.window_ev, prm.window_mode)
     CoK, CvK = Co[:, occK], Cv[:, virK]
-    # Coulomb factor
-    V3 = I.int3c(coords, shells, auxJ, None, pair_mask)  # [nao, nao, naux]
-    Tia = np.einsum("mi,mnP,na->Pia", Co, V3, Cv, optimize=True)
+    # Coulomb factor (integrals evaluated a few auxiliary shells at a time to bound memory)
+    Tia = _transformed(coords, shells, auxJ, 1.0, 0.0, None, pair_mask, Co, Cv)
     B_ia, L_J = cholesky_split(Tia, I.int2c(coords, auxJ))
-    del V3
     # exchange factors in the J^ metric
     Bx_ij, Bx_ab, L_K = _exchange_factors(coords, shells, auxK, prm, pair_mask, CoK, CvK)
     e = mol.mo_energy
@@ -185,12 +183,21 @@ def build_factors(mol, prm: Params = Params(), pair_mask=None) -> Factors:
                    occK=occK, virK=virK, L_J=L_J, L_K=L_K, pairs=pairs)
 
 
+def _transformed(coords, shells, aux, alpha, beta, omega, mask, Cl, Cr, chunk=8):
+    """T~[P][p][q] = sum_mu nu Cl[mu][p] (mu nu| alpha/r + beta erf(omega r)/r |P) Cr[nu][q]."""
+    out = []
+    for s0 in range(0, len(aux), chunk):
+        idx = list(range(s0, min(len(aux), s0 + chunk)))
+        V3 = _operator_int3c(coords, shells, aux, alpha, beta, omega, mask, idx)
+        out.append(np.einsum("mp,mnP,nq->Ppq", Cl, V3, Cr, optimize=True))
+    return np.concatenate(out, axis=0)
+
+
 def _exchange_factors(coords, shells, auxK, prm, pair_mask, CoK, CvK):
     def one(alpha, beta):
-        V3 = _operator_int3c(coords, shells, auxK, alpha, beta, prm.omega, pair_mask)
         V2 = _operator_int2c(coords, auxK, alpha, beta, prm.omega)
-        Tij = np.einsum("mi,mnP,nj->Pij", CoK, V3, CoK, optimize=True)
-        Tab = np.einsum("ma,mnP,nb->Pab", CvK, V3, CvK, optimize=True)
+        Tij = _transformed(coords, shells, auxK, alpha, beta, prm.omega, pair_mask, CoK, CoK)
+        Tab = _transformed(coords, shells, auxK, alpha, beta, prm.omega, pair_mask, CvK, CvK)
         L = np.linalg.cholesky(V2)
         nK = V2.shape[0]
         Bij = sla.solve_triangular(L, Tij.reshape(nK, -1), lower=True).reshape(Tij.shape)

@@ -1,0 +1,502 @@
+// Factor build (auxiliary basis, window, screening, metric Cholesky, 3-centre integrals, MO
+// transforms, metric application, storage precision) and the sigma product A X.
+#include <algorithm>
+#include <cmath>
+
+#include "factors.hpp"
+#include "linalg.hpp"
+
+int64_t risp_factors::bytes() const {
+  return (int64_t)(t_ia.bytes() + t_ij.bytes() + t_ab.bytes() + t_ia32.bytes() + t_ij32.bytes() +
+                   t_ab32.bytes() + scale_ia.bytes() + scale_ia2.bytes() + scale_k.bytes() + occ_k.bytes() +
+                   vir_k.bytes() + pos_o.bytes() + pos_v.bytes() + de64.bytes() + de32.bytes() +
+                   ws_y.bytes() + ws_ybf.bytes() + ws_xbf.bytes() + ws_xw.bytes() + ws_mt.bytes() +
+                   ws_k.bytes() + ws_split.bytes());
+}
+
+namespace risp {
+
+void validate_system(const risp_system* sys) {
+  RISP_CHECK(sys != nullptr, RISP_E_ARG, "system is NULL");
+  RISP_CHECK(sys->natm > 0 && sys->coords && sys->Z && sys->aux_radius, RISP_E_ARG,
+             "system: atoms, coordinates, charges and radii are required");
+  RISP_CHECK(sys->nshell > 0 && sys->shells, RISP_E_ARG, "system: AO shells are required");
+  RISP_CHECK(sys->mo_coeff && sys->mo_energy, RISP_E_ARG, "system: MO coefficients and energies are required");
+  int nf = 0;
+  for (int k = 0; k < sys->nshell; ++k) {
+    const risp_shell& s = sys->shells[k];
+    RISP_CHECK(s.l == 0 || s.l == 1, RISP_E_ARG, "only s and p shells are supported");
+    RISP_CHECK(s.atom >= 0 && s.atom < sys->natm, RISP_E_ARG, "shell atom index out of range");
+    RISP_CHECK(s.exponent > 0.0 && std::isfinite(s.exponent), RISP_E_ARG, "shell exponent must be positive");
+    nf += s.l == 0 ? 1 : 3;
+  }
+  RISP_CHECK(nf == sys->nao, RISP_E_SHAPE, "nao does not match the shells");
+  RISP_CHECK(sys->nmo > 0 && sys->nmo <= sys->nao, RISP_E_SHAPE, "need 0 < nmo <= nao");
+  RISP_CHECK(sys->nocc > 0 && sys->nocc < sys->nmo, RISP_E_SHAPE, "need 0 < nocc < nmo");
+  for (int a = 0; a < sys->natm; ++a)
+    RISP_CHECK(sys->aux_radius[a] > 0.0, RISP_E_ARG, "auxiliary radius must be positive");
+}
+
+void select_aux(const risp_system* sys, const risp_params* prm, std::vector<risp_shell>& J,
+                std::vector<risp_shell>& K) {
+  J.clear();
+  K.clear();
+  for (int a = 0; a < sys->natm; ++a) {
+    if (sys->Z[a] == 1 && !prm->h_in_aux) continue;
+    const double r = sys->aux_radius[a];
+    const double e = prm->theta / (r * r);
+    J.push_back({a, 0, e, 1.0});
+    J.push_back({a, 1, e, 1.0});
+    K.push_back({a, 0, e, 1.0});
+  }
+}
+
+static Gemm g64(int M, int N, int K) {
+  Gemm g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.tin = g.tout = DType::F64;
+  return g;
+}
+
+// Stored factor of `rows` auxiliary slices of `cols` values, from the FP64 matrix B [rows][cols].
+struct Stored {
+  DevBuf main, f32, scale;
+};
+static void store_factor(const double* B, int rows, int64_t cols, int precision, bool keep_f32,
+                         bool bf16_scale, Stored& out, hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  if (precision == RISP_FP64) {
+    out.main.alloc(std::max<int64_t>(n, 1) * 8);
+    convert(B, DType::F64, out.main.get(), DType::F64, n, s);
+  } else if (precision == RISP_FP32) {
+    out.main.alloc(std::max<int64_t>(n, 1) * 4);
+    convert(B, DType::F64, out.main.get(), DType::F32, n, s);
+  } else {
+    out.main.alloc(std::max<int64_t>(n, 1) * 2);
+    out.scale.alloc(std::max(rows, 1) * sizeof(float));
+    if (bf16_scale) {
+      scale_rows_bf16(B, rows, cols, out.scale.as<float>(), out.main.get(), s);
+    } else {
+      std::vector<float> ones(std::max(rows, 1), 1.0f);
+      RISP_HIP(hipMemcpyAsync(out.scale.get(), ones.data(), ones.size() * 4, hipMemcpyHostToDevice, s));
+      convert(B, DType::F64, out.main.get(), DType::BF16, n, s);
+      RISP_HIP(hipStreamSynchronize(s));
+    }
+    if (keep_f32) {
+      out.f32.alloc(std::max<int64_t>(n, 1) * 4);
+      convert(B, DType::F64, out.f32.get(), DType::F32, n, s);
+    }
+  }
+}
+
+__global__ void k_mul_scales(const float* a, const float* b, float* c, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) c[t] = a[t] * b[t];
+}
+
+// T~[P][p][q] = C_l^T (mu nu|P) C_r over auxiliary shells, chunked; V = (mu nu|op|P) FP64.
+// CLT [nl][nao], CRT [nr][nao] (transposed MO coefficient blocks). Out: FP64 [nfunc][nl][nr].
+static void transformed_3c(risp_ctx* ctx, const DevShells& ao, const PairList& pairs,
+                           const DevShells& aux, const Operator& op, const double* CLT, int nl,
+                           const double* CRT, int nr, double* out) {
+  hipStream_t s = ctx->stream;
+  const int nao = ao.nfunc;
+  // auxiliary shell chunks of at most ~2 GB of FP64 integrals
+  const int64_t per_func = (int64_t)nao * nao * 8;
+  const int max_f = (int)std::max<int64_t>(3, std::min<int64_t>(256, (2ll << 30) / per_func));
+  std::vector<int> l(aux.n);
+  RISP_HIP(hipMemcpyAsync(l.data(), aux.l.get(), aux.n * sizeof(int), hipMemcpyDeviceToHost, s));
+  RISP_HIP(hipStreamSynchronize(s));
+  DevBuf V((size_t)max_f * nao * nao * 8 + 8);
+  DevBuf G((size_t)max_f * std::max(nl, 1) * nao * 8 + 8);
+  int f0 = 0;
+  for (int s0 = 0; s0 < aux.n;) {
+    int s1 = s0, nf = 0;
+    while (s1 < aux.n && nf + (l[s1] == 0 ? 1 : 3) <= max_f) nf += l[s1++] == 0 ? 1 : 3;
+    int3c(ao, pairs, aux, s0, s1, op, ctx->boys.as<double>(), V.as<double>(), s);
+    // G[P][i][mu] = sum_nu CLT[i][nu] V[P][mu][nu]   (V symmetric in mu, nu)
+    Gemm g = g64(nl, nao, nao);
+    g.A = CLT;
+    g.lda = nao;
+    g.B = V.get();
+    g.ldb = nao;
+    g.C = G.get();
+    g.ldc = nao;
+    g.nb2 = nf;
+    g.sb2 = (int64_t)nao * nao;
+    g.sc2 = (int64_t)nl * nao;
+    gemm(g, nullptr, s);
+    // out[P][i][a] = sum_mu G[P][i][mu] CRT[a][mu]
+    Gemm h = g64(nl, nr, nao);
+    h.A = G.get();
+    h.lda = nao;
+    h.sa2 = (int64_t)nl * nao;
+    h.B = CRT;
+    h.ldb = nao;
+    h.C = out + (int64_t)f0 * nl * nr;
+    h.ldc = nr;
+    h.sc2 = (int64_t)nl * nr;
+    h.nb2 = nf;
+    gemm(h, nullptr, s);
+    f0 += nf;
+    s0 = s1;
+  }
+  RISP_HIP(hipStreamSynchronize(s));
+}
+
+// B = L^-1 T~ over the auxiliary index: T~ [n][cols] -> B [n][cols] (FP64), in ov-column chunks.
+static void metric_apply(const double* Linv, int n, const double* T, int64_t cols, double* B, hipStream_t s) {
+  const int64_t chunk = 1ll << 24;
+  for (int64_t c0 = 0; c0 < cols; c0 += chunk) {
+    const int nc = (int)std::min<int64_t>(chunk, cols - c0);
+    Gemm g = g64(n, nc, n);
+    g.A = Linv;
+    g.lda = n;
+    g.B = T + c0;  // B[j][k] = T[k][c0 + j]
+    g.ldb = cols;
+    g.b_kc = false;
+    g.C = B + c0;
+    g.ldc = cols;
+    gemm(g, nullptr, s);
+  }
+}
+
+static void metric_inverse_cholesky(risp_ctx* ctx, const DevShells& aux, const Operator& op, DevBuf& Linv) {
+  hipStream_t s = ctx->stream;
+  const int n = aux.nfunc;
+  DevBuf V((size_t)n * n * 8);
+  int2c(aux, op, ctx->boys.as<double>(), V.as<double>(), s);
+  cholesky(V.as<double>(), n, s);
+  Linv.alloc((size_t)n * n * 8);
+  tri_inverse(V.as<double>(), Linv.as<double>(), n, s);
+  RISP_HIP(hipStreamSynchronize(s));
+}
+
+void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, risp_factors* f) {
+  validate_system(sys);
+  RISP_CHECK(prm != nullptr, RISP_E_ARG, "params is NULL");
+  RISP_CHECK(prm->precision >= RISP_FP64 && prm->precision <= RISP_BF16, RISP_E_ARG, "bad precision");
+  RISP_CHECK(prm->rsh_mode == RISP_RSH_COMBINED || prm->rsh_mode == RISP_RSH_SPLIT, RISP_E_ARG, "bad rsh_mode");
+  RISP_CHECK(prm->window_mode == RISP_WIN_ABSOLUTE || prm->window_mode == RISP_WIN_FRONTIER, RISP_E_ARG,
+             "bad window_mode");
+  RISP_CHECK(prm->theta > 0.0 && prm->schwarz_tau >= 0.0 && prm->omega >= 0.0, RISP_E_ARG,
+             "theta must be positive, tau and omega non-negative");
+  RISP_CHECK(prm->beta == 0.0 || prm->omega > 0.0, RISP_E_ARG, "beta != 0 needs omega > 0");
+  hipStream_t s = ctx->stream;
+  const int nao = sys->nao, nmo = sys->nmo, nocc = sys->nocc, nvir = nmo - nocc;
+  f->ctx = ctx;
+  f->nao = nao;
+  f->nmo = nmo;
+  f->nocc = nocc;
+  f->nvir = nvir;
+  f->precision = prm->precision;
+  f->has_f32 = prm->precision == RISP_BF16;
+
+  // auxiliary bases (section on exchange-space truncation: H omitted, J = s + p, K = s)
+  std::vector<risp_shell> auxJ, auxK;
+  select_aux(sys, prm, auxJ, auxK);
+  RISP_CHECK(!auxJ.empty(), RISP_E_ARG, "no auxiliary functions (all atoms are hydrogen)");
+
+  DevShells ao, aj, ak;
+  upload_shells(ao, sys->coords, sys->shells, sys->nshell, s);
+  upload_shells(aj, sys->coords, auxJ.data(), (int)auxJ.size(), s);
+  upload_shells(ak, sys->coords, auxK.data(), (int)auxK.size(), s);
+  f->naux_j = aj.nfunc;
+
+  DevBuf C = upload(sys->mo_coeff, (size_t)nao * nmo, s);
+  DevBuf E = upload(sys->mo_energy, (size_t)nmo, s);
+
+  // window
+  f->occ_k.alloc(std::max(nocc, 1) * sizeof(int));
+  f->vir_k.alloc(std::max(nvir, 1) * sizeof(int));
+  window_sets(E.as<double>(), nmo, nocc, prm->window_ev, prm->window_mode, f->occ_k.as<int>(), &f->nok,
+              f->vir_k.as<int>(), &f->nvk, s);
+  f->pos_o.alloc(std::max(nocc, 1) * sizeof(int));
+  f->pos_v.alloc(std::max(nvir, 1) * sizeof(int));
+  window_positions(f->occ_k.as<int>(), f->nok, nocc, f->pos_o.as<int>(), s);
+  window_positions(f->vir_k.as<int>(), f->nvk, nvir, f->pos_v.as<int>(), s);
+
+  // screening against the Coulomb auxiliary basis
+  const double qaux = std::sqrt(aux_diag_max(aj, ctx->boys.as<double>(), s));
+  PairList pairs;
+  screen_pairs(ao, qaux, prm->schwarz_tau, false, pairs, s);
+  f->npair = pairs.n;
+
+  // transposed MO blocks
+  DevBuf CoT((size_t)nocc * nao * 8), CvT((size_t)nvir * nao * 8);
+  gather_transpose(C.as<double>(), nmo, nao, nullptr, 0, nocc, CoT.as<double>(), s);
+  gather_transpose(C.as<double>(), nmo, nao, nullptr, nocc, nvir, CvT.as<double>(), s);
+
+  // ---- Coulomb factor T_ia ----
+  {
+    Operator coul;  // 1/r
+    DevBuf Linv;
+    metric_inverse_cholesky(ctx, aj, coul, Linv);
+    const int64_t ov = (int64_t)nocc * nvir;
+    DevBuf Tt((size_t)aj.nfunc * ov * 8);
+    transformed_3c(ctx, ao, pairs, aj, coul, CoT.as<double>(), nocc, CvT.as<double>(), nvir, Tt.as<double>());
+    DevBuf B((size_t)aj.nfunc * ov * 8);
+    metric_apply(Linv.as<double>(), aj.nfunc, Tt.as<double>(), ov, B.as<double>(), s);
+    Tt.release();
+    Stored st;
+    store_factor(B.as<double>(), aj.nfunc, ov, prm->precision, f->has_f32, prm->bf16_scale != 0, st, s);
+    RISP_HIP(hipStreamSynchronize(s));
+    f->t_ia = std::move(st.main);
+    f->t_ia32 = std::move(st.f32);
+    f->scale_ia = std::move(st.scale);
+    if (prm->precision == RISP_BF16) {
+      f->scale_ia2.alloc(aj.nfunc * sizeof(float));
+      k_mul_scales<<<ceil_div(aj.nfunc, 256), 256, 0, s>>>(f->scale_ia.as<float>(), f->scale_ia.as<float>(),
+                                                          f->scale_ia2.as<float>(), aj.nfunc);
+      RISP_LAUNCHED();
+    }
+  }
+
+  // ---- exchange factors T_ij, T_ab in the J^ metric ----
+  std::vector<Operator> blocks;
+  if (prm->c_x != 0.0 || prm->beta != 0.0) {
+    if (prm->rsh_mode == RISP_RSH_COMBINED) {
+      blocks.push_back({prm->c_x, prm->beta, prm->omega});
+    } else {
+      if (prm->c_x != 0.0) blocks.push_back({prm->c_x, 0.0, 0.0});
+      if (prm->beta != 0.0) blocks.push_back({0.0, prm->beta, prm->omega});
+    }
+  }
+  const int nks = ak.nfunc;
+  f->naux_k = (int)blocks.size() * nks;
+  const int nok = f->nok, nvk = f->nvk;
+  if (f->naux_k > 0 && nok > 0 && nvk > 0) {
+    DevBuf CoKT((size_t)nok * nao * 8), CvKT((size_t)nvk * nao * 8);
+    gather_transpose(C.as<double>(), nmo, nao, f->occ_k.as<int>(), 0, nok, CoKT.as<double>(), s);
+    // virtual window columns are nocc + vir_k[b]: gather through a shifted index list
+    {
+      std::vector<int> hv(nvk);
+      RISP_HIP(hipMemcpyAsync(hv.data(), f->vir_k.get(), nvk * sizeof(int), hipMemcpyDeviceToHost, s));
+      RISP_HIP(hipStreamSynchronize(s));
+      for (int& v : hv) v += nocc;
+      DevBuf dv = upload(hv.data(), hv.size(), s);
+      gather_transpose(C.as<double>(), nmo, nao, dv.as<int>(), 0, nvk, CvKT.as<double>(), s);
+      RISP_HIP(hipStreamSynchronize(s));
+    }
+    const int nK = f->naux_k;
+    DevBuf Bij((size_t)nK * nok * nok * 8), Bab((size_t)nK * nvk * nvk * 8);
+    for (size_t blk = 0; blk < blocks.size(); ++blk) {
+      DevBuf Linv;
+      metric_inverse_cholesky(ctx, ak, blocks[blk], Linv);
+      DevBuf Tij((size_t)nks * nok * nok * 8), Tab((size_t)nks * nvk * nvk * 8);
+      transformed_3c(ctx, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
+                     Tij.as<double>());
+      transformed_3c(ctx, ao, pairs, ak, blocks[blk], CvKT.as<double>(), nvk, CvKT.as<double>(), nvk,
+                     Tab.as<double>());
+      metric_apply(Linv.as<double>(), nks, Tij.as<double>(), (int64_t)nok * nok,
+                   Bij.as<double>() + blk * (size_t)nks * nok * nok, s);
+      metric_apply(Linv.as<double>(), nks, Tab.as<double>(), (int64_t)nvk * nvk,
+                   Bab.as<double>() + blk * (size_t)nks * nvk * nvk, s);
+      RISP_HIP(hipStreamSynchronize(s));
+    }
+    // T_ij stored [i][P][j] for the second exchange product; T_ab [P][a][b]
+    Stored sij, sab;
+    store_factor(Bij.as<double>(), nK, (int64_t)nok * nok, prm->precision, f->has_f32, prm->bf16_scale != 0, sij, s);
+    store_factor(Bab.as<double>(), nK, (int64_t)nvk * nvk, prm->precision, f->has_f32, prm->bf16_scale != 0, sab, s);
+    const size_t esz = prm->precision == RISP_FP64 ? 8 : (prm->precision == RISP_FP32 ? 4 : 2);
+    f->t_ij.alloc(std::max<size_t>((size_t)nK * nok * nok * esz, 8));
+    permute_pij_ipj(sij.main.get(), nK, nok, nok, esz, f->t_ij.get(), s);
+    f->t_ab = std::move(sab.main);
+    if (f->has_f32) {
+      f->t_ij32.alloc(std::max<size_t>((size_t)nK * nok * nok * 4, 8));
+      permute_pij_ipj(sij.f32.get(), nK, nok, nok, 4, f->t_ij32.get(), s);
+      f->t_ab32 = std::move(sab.f32);
+    }
+    if (prm->precision == RISP_BF16) {
+      f->scale_k.alloc(nK * sizeof(float));
+      k_mul_scales<<<ceil_div(nK, 256), 256, 0, s>>>(sij.scale.as<float>(), sab.scale.as<float>(),
+                                                    f->scale_k.as<float>(), nK);
+      RISP_LAUNCHED();
+    }
+    RISP_HIP(hipStreamSynchronize(s));
+  } else {
+    f->naux_k = 0;
+  }
+
+  // orbital gaps
+  f->de64.alloc((size_t)nocc * nvir * 8);
+  f->de32.alloc((size_t)nocc * nvir * 4);
+  orbital_gaps(E.as<double>(), nocc, nvir, f->de64.as<double>(), f->de32.as<float>(), s);
+  RISP_HIP(hipStreamSynchronize(s));
+}
+
+// -------------------------------------------------------------------------------------------
+// sigma = A X
+// -------------------------------------------------------------------------------------------
+double sigma_flops(const risp_factors* f, int m) {
+  const double ov = (double)f->nocc * f->nvir;
+  double fl = 4.0 * ov * f->naux_j * m + ov * m;
+  if (f->naux_k > 0)
+    fl += 2.0 * f->naux_k * (double)f->nok * f->nvk * m * (double)(f->nok + f->nvk);
+  return fl;
+}
+
+constexpr int kMaxSplit = 1024;
+
+// Workspaces are sized for the largest block and the widest compute type seen so far (BF16
+// factors also run FP32 products in the correction pass).
+static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
+  const int csz = tc == DType::F64 ? 8 : (tc == DType::F32 ? 4 : 2);
+  if (m <= f->ws_m && csz <= f->ws_csz) return;
+  RISP_HIP(hipStreamSynchronize(s));  // workspaces may be in use by queued work
+  m = std::max(m, f->ws_m);
+  const int cs = std::max(csz, f->ws_csz);
+  const int64_t ov = (int64_t)f->nocc * f->nvir;
+  const size_t acc = cs == 8 ? 8 : 4;
+  f->ws_y.alloc((size_t)f->naux_j * m * acc);
+  f->ws_ybf.alloc((size_t)f->naux_j * m * 2 + 16);
+  f->ws_xbf.alloc((size_t)m * ov * 2 + 16);
+  f->ws_split.alloc((size_t)kMaxSplit * f->naux_j * m * acc);
+  if (f->naux_k > 0 && f->nok > 0 && f->nvk > 0) {
+    const int64_t per_p = (int64_t)m * f->nvk * f->nok;
+    // P-chunk: intermediate M at most ~1 GiB and at least one slice
+    const int64_t pc = std::max<int64_t>(1, std::min<int64_t>(f->naux_k, (1ll << 30) / (per_p * cs)));
+    f->ws_xw.alloc((size_t)m * f->nok * f->nvk * cs);
+    f->ws_mt.alloc((size_t)per_p * pc * cs);
+    f->ws_k.alloc((size_t)m * f->nok * f->nvk * acc);
+  }
+  f->ws_m = m;
+  f->ws_csz = cs;
+}
+
+static void need(const DevBuf& b, size_t bytes, const char* what) {
+  RISP_CHECK(b.bytes() >= bytes, RISP_E_STATE, std::string("sigma workspace too small: ") + what);
+}
+
+void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s) {
+  if (m <= 0) return;
+  const bool bf = f->precision == RISP_BF16 && !use_f32;
+  const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
+  const DType tv = f->precision == RISP_FP64 ? DType::F64 : DType::F32;  // X / sigma type
+  const DType tacc = tc == DType::F64 ? DType::F64 : DType::F32;
+  ensure_workspace(f, m, tc, s);
+  const int64_t ov = (int64_t)f->nocc * f->nvir;
+  const int nJ = f->naux_j;
+  need(f->ws_y, (size_t)nJ * m * dtype_size(tacc), "Y");
+  if (bf) {
+    need(f->ws_xbf, (size_t)m * ov * 2, "X (BF16)");
+    need(f->ws_ybf, (size_t)nJ * m * 2, "Y (BF16)");
+  }
+  const void* Tia = (f->precision == RISP_BF16 && use_f32) ? f->t_ia32.get() : f->t_ia.get();
+  const void* Tij = (f->precision == RISP_BF16 && use_f32) ? f->t_ij32.get() : f->t_ij.get();
+  const void* Tab = (f->precision == RISP_BF16 && use_f32) ? f->t_ab32.get() : f->t_ab.get();
+
+  // Coulomb pass 1: Y[P][m] = s_P^2 sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
+  const void* Xc = X;
+  if (bf) {
+    convert(X, DType::F32, f->ws_xbf.get(), DType::BF16, m * ov, s);
+    Xc = f->ws_xbf.get();
+  }
+  const float* rs = bf ? f->scale_ia2.as<float>() : nullptr;  // s_P^2 folded into Y (exact)
+  {
+    Gemm g;
+    g.M = nJ;
+    g.N = m;
+    g.K = (int)ov;
+    RISP_CHECK(ov < (1ll << 31), RISP_E_SHAPE, "nocc*nvir too large");
+    g.tin = tc;
+    g.tout = tacc;
+    g.A = Tia;
+    g.lda = ov;
+    g.B = Xc;
+    g.ldb = ov;
+    g.C = f->ws_y.get();
+    g.ldc = m;
+    g.row_scale = rs;
+    g.ksplit = std::min(kMaxSplit, gemm_auto_split(g));
+    need(f->ws_split, gemm_workspace_bytes(g), "split-K");
+    gemm(g, f->ws_split.get(), s);
+  }
+  // Coulomb pass 2: sigma[m][ia] = 2 sum_P Y[P][m] T_ia[P][ia]
+  {
+    const void* Yc = f->ws_y.get();
+    if (bf) {
+      convert(f->ws_y.get(), DType::F32, f->ws_ybf.get(), DType::BF16, (int64_t)nJ * m, s);
+      Yc = f->ws_ybf.get();
+    }
+    Gemm g;
+    g.M = m;
+    g.N = (int)ov;
+    g.K = nJ;
+    g.tin = tc;
+    g.tout = tv;
+    g.A = Yc;  // A[mm][P] = Y[P][mm]
+    g.lda = m;
+    g.a_kc = false;
+    g.B = Tia;  // B[ia][P] = T[P][ia]
+    g.ldb = ov;
+    g.b_kc = false;
+    g.C = sig;
+    g.ldc = ov;
+    g.alpha = 2.0;
+    gemm(g, nullptr, s);
+  }
+  // exchange inside the window
+  const int nK = f->naux_k, nok = f->nok, nvk = f->nvk;
+  const bool exch = nK > 0 && nok > 0 && nvk > 0;
+  if (exch) {
+    gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
+                  f->ws_xw.get(), tc, s);
+    const size_t csz = dtype_size(tc);
+    const int64_t per_p = (int64_t)m * nvk * nok;
+    const int pc = (int)std::min<int64_t>(nK, f->ws_mt.bytes() / (per_p * csz));
+    RISP_CHECK(pc >= 1, RISP_E_STATE, "sigma workspace too small for one auxiliary slice");
+    need(f->ws_xw, (size_t)per_p * csz, "Xw");
+    need(f->ws_k, (size_t)per_p * dtype_size(tacc), "K");
+    for (int P0 = 0; P0 < nK; P0 += pc) {
+      const int np = std::min(pc, nK - P0);
+      // GEMM1: Mt[m][a][(p, j)] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]
+      Gemm g1;
+      g1.M = nvk;
+      g1.N = nok;
+      g1.K = nvk;
+      g1.tin = tc;
+      g1.tout = tc;
+      g1.A = static_cast<const char*>(Tab) + (size_t)P0 * nvk * nvk * csz;
+      g1.lda = nvk;
+      g1.B = f->ws_xw.get();
+      g1.ldb = nvk;
+      g1.C = f->ws_mt.get();
+      g1.ldc = (int64_t)np * nok;
+      g1.nb1 = m;
+      g1.nb2 = np;
+      g1.sa1 = 0;
+      g1.sa2 = (int64_t)nvk * nvk;
+      g1.sb1 = (int64_t)nok * nvk;
+      g1.sb2 = 0;
+      g1.sc1 = (int64_t)nvk * np * nok;
+      g1.sc2 = nok;
+      g1.batch_scale = bf ? f->scale_k.as<float>() + P0 : nullptr;
+      gemm(g1, nullptr, s);
+      // GEMM2: K[m][i][a] += sum_(p, j) T_ij[i][(P0 + p) j] Mt[m][a][(p, j)]
+      Gemm g2;
+      g2.M = nok;
+      g2.N = nvk;
+      g2.K = np * nok;
+      g2.tin = tc;
+      g2.tout = tacc;
+      g2.A = static_cast<const char*>(Tij) + (size_t)P0 * nok * csz;
+      g2.lda = (int64_t)nK * nok;
+      g2.B = f->ws_mt.get();
+      g2.ldb = (int64_t)np * nok;
+      g2.C = f->ws_k.get();
+      g2.ldc = nvk;
+      g2.nb2 = m;
+      g2.sb2 = (int64_t)nvk * np * nok;
+      g2.sc2 = (int64_t)nok * nvk;
+      g2.beta = P0 > 0 ? 1.0 : 0.0;
+      gemm(g2, nullptr, s);
+    }
+  }
+  combine_sigma(sig, X, tv, f->de64.as<double>(), f->de32.as<float>(), m, f->nocc, f->nvir,
+                exch ? f->ws_k.get() : nullptr, tacc, f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk, s);
+}
+
+}  // namespace risp

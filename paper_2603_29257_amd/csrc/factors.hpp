@@ -1,0 +1,54 @@
+// The factor object, the factor build and the sigma product.
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+#include "integrals.hpp"
+
+#include <set>
+
+struct risp_factors;
+
+struct risp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  risp::DevBuf boys;                // Boys-function Taylor table
+  std::set<risp_factors*> factors;  // live factor objects (detached when the context goes away)
+};
+
+struct risp_factors {
+  risp_ctx* ctx = nullptr;
+  int nao = 0, nmo = 0, nocc = 0, nvir = 0;
+  int naux_j = 0, naux_k = 0, nok = 0, nvk = 0, npair = 0;
+  int precision = RISP_FP32;
+  bool has_f32 = false;  // FP32 copies kept next to BF16 factors (correction pass)
+  risp::DevBuf t_ia, t_ij, t_ab;           // stored precision
+  risp::DevBuf t_ia32, t_ij32, t_ab32;     // FP32 copies (BF16 mode)
+  risp::DevBuf scale_ia, scale_ia2, scale_k;  // BF16 power-of-two scales (s_P, s_P^2, s_ij s_ab)
+  risp::DevBuf occ_k, vir_k, pos_o, pos_v; // window index sets and inverse maps
+  risp::DevBuf de64, de32;                 // e_a - e_i
+  // sigma workspaces, sized for ws_m trial vectors
+  int ws_m = 0;
+  int ws_csz = 0;  // bytes per element of the compute type the workspaces were sized for
+  risp::DevBuf ws_y, ws_ybf, ws_xbf, ws_xw, ws_mt, ws_k, ws_split;
+  double t_build = 0.0;  // seconds spent in the factor build
+  int64_t bytes() const;
+};
+
+namespace risp {
+
+// precision of the sigma arithmetic: FP64 factors -> FP64, FP32 -> FP32, BF16 -> BF16 with FP32
+// accumulation; `use_f32` selects the FP32 copies of BF16 factors.
+void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s);
+
+// algorithmic flops of one sigma block of m vectors
+double sigma_flops(const risp_factors* f, int m);
+
+void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, risp_factors* f);
+
+void validate_system(const risp_system* sys);
+void select_aux(const risp_system* sys, const risp_params* prm, std::vector<risp_shell>& J,
+                std::vector<risp_shell>& K);
+
+}  // namespace risp

@@ -1,0 +1,53 @@
+// Batched MFMA matrix products for gfx950: C = alpha * s_b * r_i * (A . B^T) + beta * C.
+//
+// A is M x K and B is N x K (the contraction index k is shared). Each operand is stored either
+// k-contiguous (A[i][k] at A + i*lda + k) or mn-contiguous (A[i][k] at A + k*lda + i); C is
+// row-major M x N. Batches are two-level, b = b1 * nb2 + b2, with separate strides for each level.
+// Products are FP64 (v_mfma_f64_16x16x4f64; operands stored as FP64 or FP32), FP32
+// (v_mfma_f32_16x16x4f32) or BF16 (v_mfma_f32_16x16x32_bf16); accumulation is FP64 for FP64
+// products and FP32 otherwise. Optional
+// factors: r_i (row_scale[i], FP32) and s_b (batch_scale[b2], FP32). Split-K writes partial sums to
+// a workspace and reduces them in a fixed order, so results do not depend on scheduling.
+#pragma once
+
+#include "common.hpp"
+
+namespace risp {
+
+// Same: the operand is stored in the product type.
+enum class DType : int { F64 = 0, F32 = 1, BF16 = 2, Same = 3 };
+
+inline size_t dtype_size(DType t) { return t == DType::F64 ? 8 : (t == DType::F32 ? 4 : 2); }
+
+struct Gemm {
+  int M = 0, N = 0, K = 0;
+  DType tin = DType::F32;  // type the products are formed in
+  DType tout = DType::F32; // type of C
+  // storage of A and B when it differs from tin (FP64 products of FP32 data, subspace algebra)
+  DType mem_a = DType::Same, mem_b = DType::Same;
+  const void* A = nullptr;
+  int64_t lda = 0;
+  bool a_kc = true;
+  const void* B = nullptr;
+  int64_t ldb = 0;
+  bool b_kc = true;
+  void* C = nullptr;
+  int64_t ldc = 0;
+  int nb1 = 1, nb2 = 1;
+  int64_t sa1 = 0, sa2 = 0, sb1 = 0, sb2 = 0, sc1 = 0, sc2 = 0;
+  double alpha = 1.0, beta = 0.0;
+  const float* row_scale = nullptr;
+  const float* batch_scale = nullptr;
+  int ksplit = 1;  // > 1 splits K over blocks (uses workspace)
+};
+
+// Launch on stream s. `work` must hold ksplit * nb1 * nb2 * M * N accumulator elements when
+// ksplit > 1 (gemm_workspace_bytes).
+size_t gemm_workspace_bytes(const Gemm& g);
+void gemm(const Gemm& g, void* work, hipStream_t s);
+
+// Choose a split-K factor so that the grid covers the chip (about 2048 blocks) for skinny
+// products; returns 1 when tiles alone suffice.
+int gemm_auto_split(const Gemm& g);
+
+}  // namespace risp

@@ -1,0 +1,378 @@
+// Blocked FP64 Cholesky and triangular inverse (panel kernels + MFMA GEMM updates), and the small
+// gather / convert / scale kernels of the factor build and the sigma product.
+#include <algorithm>
+#include <cmath>
+
+#include "linalg.hpp"
+
+namespace risp {
+
+constexpr int kNB = 32;  // panel width
+
+__device__ __forceinline__ uint16_t f2bf_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f_(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ---- Cholesky ----
+__global__ void k_potrf_diag(double* A, int n, int j0, int jb, int* info) {
+  __shared__ double a[kNB][kNB + 1];
+  for (int t = threadIdx.x; t < jb * jb; t += blockDim.x) {
+    const int i = t / jb, j = t % jb;
+    a[i][j] = j <= i ? A[(int64_t)(j0 + i) * n + j0 + j] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < jb; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = a[k][k];
+      if (!(d > 0.0)) {
+        if (*info == 0) *info = j0 + k + 1;
+        a[k][k] = 1.0;  // keep going with a harmless pivot; the host reports the failure
+      } else {
+        a[k][k] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    for (int i = k + 1 + threadIdx.x; i < jb; i += blockDim.x) a[i][k] /= a[k][k];
+    __syncthreads();
+    for (int t = threadIdx.x; t < jb * jb; t += blockDim.x) {
+      const int i = t / jb, j = t % jb;
+      if (j > k && j <= i) a[i][j] -= a[i][k] * a[j][k];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < jb * jb; t += blockDim.x) {
+    const int i = t / jb, j = t % jb;
+    A[(int64_t)(j0 + i) * n + j0 + j] = j <= i ? a[i][j] : 0.0;
+  }
+}
+
+// rows r >= j0 + jb: A[r][j0:j0+jb] <- A[r][j0:j0+jb] L_kk^-T (forward substitution per row)
+__global__ void k_trsm_panel(double* A, int n, int j0, int jb) {
+  __shared__ double L[kNB][kNB + 1];
+  for (int t = threadIdx.x; t < jb * jb; t += blockDim.x) {
+    const int i = t / jb, j = t % jb;
+    L[i][j] = A[(int64_t)(j0 + i) * n + j0 + j];
+  }
+  __syncthreads();
+  const int r = j0 + jb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double x[kNB];
+  double* row = A + (int64_t)r * n + j0;
+  for (int c = 0; c < jb; ++c) {
+    double v = row[c];
+    for (int t = 0; t < c; ++t) v -= x[t] * L[c][t];
+    x[c] = v / L[c][c];
+  }
+  for (int c = 0; c < jb; ++c) row[c] = x[c];
+}
+
+__global__ void k_zero_upper(double* A, int n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  if (j > i) A[t] = 0.0;
+}
+
+void cholesky(double* A, int n, hipStream_t s) {
+  DevBuf info(sizeof(int));
+  RISP_HIP(hipMemsetAsync(info.get(), 0, sizeof(int), s));
+  for (int j0 = 0; j0 < n; j0 += kNB) {
+    const int jb = std::min(kNB, n - j0);
+    k_potrf_diag<<<1, 256, 0, s>>>(A, n, j0, jb, info.as<int>());
+    RISP_LAUNCHED();
+    const int r0 = j0 + jb, nr = n - r0;
+    if (nr <= 0) break;
+    k_trsm_panel<<<ceil_div(nr, 64), 64, 0, s>>>(A, n, j0, jb);
+    RISP_LAUNCHED();
+    Gemm g;
+    g.M = nr;
+    g.N = nr;
+    g.K = jb;
+    g.tin = g.tout = DType::F64;
+    g.A = A + (int64_t)r0 * n + j0;
+    g.lda = n;
+    g.a_kc = true;
+    g.B = g.A;
+    g.ldb = n;
+    g.b_kc = true;
+    g.C = A + (int64_t)r0 * n + r0;
+    g.ldc = n;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    gemm(g, nullptr, s);
+  }
+  k_zero_upper<<<ceil_div((int64_t)n * n, 256), 256, 0, s>>>(A, n);
+  RISP_LAUNCHED();
+  int h = 0;
+  RISP_HIP(hipMemcpyAsync(&h, info.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+  RISP_HIP(hipStreamSynchronize(s));
+  RISP_CHECK(h == 0, RISP_E_ARG,
+             "auxiliary metric is not positive definite (pivot " + std::to_string(h) + ")");
+}
+
+// ---- triangular inverse ----
+// X[k0:k0+kb][0:k0+kb] <- identity block (ones on the diagonal of the kb x kb block)
+__global__ void k_set_rhs(double* X, int n, int k0, int kb) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int ncol = k0 + kb;
+  if (t >= (int64_t)kb * ncol) return;
+  const int r = (int)(t / ncol), c = (int)(t % ncol);
+  X[(int64_t)(k0 + r) * n + c] = (c == k0 + r) ? 1.0 : 0.0;
+}
+
+// solve L_kk Y = X[k0:k0+kb][c] for each column c < k0 + kb (one thread per column)
+__global__ void k_trsv_block(const double* L, double* X, int n, int k0, int kb) {
+  __shared__ double Lk[kNB][kNB + 1];
+  for (int t = threadIdx.x; t < kb * kb; t += blockDim.x) {
+    const int i = t / kb, j = t % kb;
+    Lk[i][j] = L[(int64_t)(k0 + i) * n + k0 + j];
+  }
+  __syncthreads();
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k0 + kb) return;
+  double y[kNB];
+  for (int r = 0; r < kb; ++r) {
+    double v = X[(int64_t)(k0 + r) * n + c];
+    for (int t = 0; t < r; ++t) v -= Lk[r][t] * y[t];
+    y[r] = v / Lk[r][r];
+  }
+  for (int r = 0; r < kb; ++r) X[(int64_t)(k0 + r) * n + c] = y[r];
+}
+
+void tri_inverse(const double* L, double* X, int n, hipStream_t s) {
+  RISP_HIP(hipMemsetAsync(X, 0, (size_t)n * n * sizeof(double), s));
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int kb = std::min(kNB, n - k0);
+    k_set_rhs<<<ceil_div((int64_t)kb * (k0 + kb), 256), 256, 0, s>>>(X, n, k0, kb);
+    RISP_LAUNCHED();
+    if (k0 > 0) {
+      // X[k0:k0+kb][0:k0] -= L[k0:k0+kb][0:k0] X[0:k0][0:k0]
+      Gemm g;
+      g.M = kb;
+      g.N = k0;
+      g.K = k0;
+      g.tin = g.tout = DType::F64;
+      g.A = L + (int64_t)k0 * n;
+      g.lda = n;
+      g.a_kc = true;
+      g.B = X;  // B[j][k] = X[k][j]
+      g.ldb = n;
+      g.b_kc = false;
+      g.C = X + (int64_t)k0 * n;
+      g.ldc = n;
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      gemm(g, nullptr, s);
+    }
+    k_trsv_block<<<ceil_div(k0 + kb, 64), 64, 0, s>>>(L, X, n, k0, kb);
+    RISP_LAUNCHED();
+  }
+}
+
+// ---- data movement ----
+__global__ void k_gather_transpose(const double* __restrict__ C, int64_t ldc, int nao,
+                                   const int* __restrict__ cols, int col0, int nr,
+                                   double* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nr * nao) return;
+  const int r = (int)(t / nao), mu = (int)(t % nao);
+  const int c = cols ? cols[r] : col0 + r;
+  out[t] = C[(int64_t)mu * ldc + c];
+}
+
+void gather_transpose(const double* C, int64_t ldc, int nao, const int* cols, int col0, int nr,
+                      double* out, hipStream_t s) {
+  if ((int64_t)nr * nao == 0) return;
+  k_gather_transpose<<<ceil_div((int64_t)nr * nao, 256), 256, 0, s>>>(C, ldc, nao, cols, col0, nr, out);
+  RISP_LAUNCHED();
+}
+
+template <typename TS, typename TD> __device__ __forceinline__ TD cvt(TS v) { return (TD)v; }
+template <> __device__ __forceinline__ uint16_t cvt<double, uint16_t>(double v) { return f2bf_rne((float)v); }
+template <> __device__ __forceinline__ uint16_t cvt<float, uint16_t>(float v) { return f2bf_rne(v); }
+
+template <typename TS, typename TD>
+__global__ void k_convert(const TS* __restrict__ a, TD* __restrict__ b, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    b[t] = cvt<TS, TD>(a[t]);
+}
+
+void convert(const void* src, DType ts, void* dst, DType td, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, 256), 1 << 16);
+  if (ts == DType::F64 && td == DType::F32)
+    k_convert<double, float><<<grid, 256, 0, s>>>((const double*)src, (float*)dst, n);
+  else if (ts == DType::F64 && td == DType::BF16)
+    k_convert<double, uint16_t><<<grid, 256, 0, s>>>((const double*)src, (uint16_t*)dst, n);
+  else if (ts == DType::F32 && td == DType::BF16)
+    k_convert<float, uint16_t><<<grid, 256, 0, s>>>((const float*)src, (uint16_t*)dst, n);
+  else if (ts == DType::F32 && td == DType::F64)
+    k_convert<float, double><<<grid, 256, 0, s>>>((const float*)src, (double*)dst, n);
+  else if (ts == td)
+    RISP_HIP(hipMemcpyAsync(dst, src, n * dtype_size(ts), hipMemcpyDeviceToDevice, s));
+  else
+    throw Error(RISP_E_ARG, "convert: unsupported type pair");
+  RISP_LAUNCHED();
+}
+
+// one block per row: max |A[r][:]| -> power-of-two scale -> scaled BF16 row
+__global__ __launch_bounds__(256) void k_scale_rows_bf16(const double* __restrict__ A, int64_t cols,
+                                                         float* __restrict__ scale,
+                                                         uint16_t* __restrict__ dst) {
+  __shared__ double red[256];
+  const double* a = A + (int64_t)blockIdx.x * cols;
+  double m = 0.0;
+  for (int64_t c = threadIdx.x; c < cols; c += blockDim.x) m = fmax(m, fabs(a[c]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  const double mx = red[0];
+  double sc = 1.0;
+  if (mx > 0.0) {
+    int e;
+    const double f = frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+    sc = ldexp(1.0, f == 0.5 ? e - 1 : e);  // smallest power of two >= mx
+  }
+  if (threadIdx.x == 0) scale[blockIdx.x] = (float)sc;
+  const double inv = 1.0 / sc;  // exact: sc is a power of two
+  uint16_t* d = dst + (int64_t)blockIdx.x * cols;
+  for (int64_t c = threadIdx.x; c < cols; c += blockDim.x) d[c] = f2bf_rne((float)(a[c] * inv));
+}
+
+void scale_rows_bf16(const double* A, int rows, int64_t cols, float* scale, void* dst, hipStream_t s) {
+  if (rows == 0) return;
+  k_scale_rows_bf16<<<rows, 256, 0, s>>>(A, cols, scale, (uint16_t*)dst);
+  RISP_LAUNCHED();
+}
+
+template <typename T>
+__global__ void k_permute(const T* __restrict__ a, T* __restrict__ b, int nP, int ni, int nj) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nP * ni * nj;
+  if (t >= total) return;
+  // t indexes the output [i][P][j]
+  const int j = (int)(t % nj);
+  const int P = (int)((t / nj) % nP);
+  const int i = (int)(t / ((int64_t)nj * nP));
+  b[t] = a[((int64_t)P * ni + i) * nj + j];
+}
+
+void permute_pij_ipj(const void* T, int nP, int ni, int nj, size_t esz, void* out, hipStream_t s) {
+  const int64_t total = (int64_t)nP * ni * nj;
+  if (total == 0) return;
+  const unsigned grid = ceil_div(total, 256);
+  if (esz == 8) k_permute<double><<<grid, 256, 0, s>>>((const double*)T, (double*)out, nP, ni, nj);
+  else if (esz == 4) k_permute<float><<<grid, 256, 0, s>>>((const float*)T, (float*)out, nP, ni, nj);
+  else k_permute<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)T, (uint16_t*)out, nP, ni, nj);
+  RISP_LAUNCHED();
+}
+
+__global__ void k_gaps(const double* __restrict__ e, int nocc, int nvir, double* de64, float* de32) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nocc * nvir) return;
+  const int i = (int)(t / nvir), a = (int)(t % nvir);
+  const double d = e[nocc + a] - e[i];
+  de64[t] = d;
+  de32[t] = (float)d;
+}
+
+void orbital_gaps(const double* e, int nocc, int nvir, double* de64, float* de32, hipStream_t s) {
+  k_gaps<<<ceil_div((int64_t)nocc * nvir, 256), 256, 0, s>>>(e, nocc, nvir, de64, de32);
+  RISP_LAUNCHED();
+}
+
+__global__ void k_fill_neg(int* p, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = -1;
+}
+__global__ void k_positions(const int* idx, int n, int* pos) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) pos[idx[t]] = t;
+}
+
+void window_positions(const int* idx, int n, int len, int* pos, hipStream_t s) {
+  if (len > 0) {
+    k_fill_neg<<<ceil_div(len, 256), 256, 0, s>>>(pos, len);
+    RISP_LAUNCHED();
+  }
+  if (n > 0) {
+    k_positions<<<ceil_div(n, 256), 256, 0, s>>>(idx, n, pos);
+    RISP_LAUNCHED();
+  }
+}
+
+template <typename TS, typename TD>
+__global__ void k_gather_window(const TS* __restrict__ X, int m, int nocc, int nvir,
+                                const int* __restrict__ occ, int nok, const int* __restrict__ vir,
+                                int nvk, TD* __restrict__ Xw) {
+  const int64_t total = (int64_t)m * nok * nvk;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(t % nvk);
+    const int j = (int)((t / nvk) % nok);
+    const int mm = (int)(t / ((int64_t)nvk * nok));
+    Xw[t] = cvt<TS, TD>(X[((int64_t)mm * nocc + occ[j]) * nvir + vir[b]]);
+  }
+}
+
+void gather_window(const void* X, DType ts, int m, int nocc, int nvir, const int* occ, int nok,
+                   const int* vir, int nvk, void* Xw, DType td, hipStream_t s) {
+  const int64_t total = (int64_t)m * nok * nvk;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
+  if (ts == DType::F64 && td == DType::F64)
+    k_gather_window<double, double><<<grid, 256, 0, s>>>((const double*)X, m, nocc, nvir, occ, nok, vir, nvk, (double*)Xw);
+  else if (ts == DType::F32 && td == DType::F32)
+    k_gather_window<float, float><<<grid, 256, 0, s>>>((const float*)X, m, nocc, nvir, occ, nok, vir, nvk, (float*)Xw);
+  else if (ts == DType::F32 && td == DType::BF16)
+    k_gather_window<float, uint16_t><<<grid, 256, 0, s>>>((const float*)X, m, nocc, nvir, occ, nok, vir, nvk, (uint16_t*)Xw);
+  else
+    throw Error(RISP_E_ARG, "gather_window: unsupported type pair");
+  RISP_LAUNCHED();
+}
+
+template <typename T, typename TK, typename TD>
+__global__ void k_combine(T* __restrict__ sig, const T* __restrict__ X, const TD* __restrict__ de,
+                          int m, int nocc, int nvir, const TK* __restrict__ K,
+                          const int* __restrict__ po, const int* __restrict__ pv, int nok, int nvk) {
+  const int64_t ov = (int64_t)nocc * nvir;
+  const int64_t total = (int64_t)m * ov;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ia = t % ov;
+    const int mm = (int)(t / ov);
+    const int i = (int)(ia / nvir), a = (int)(ia % nvir);
+    T v = sig[t] + (T)de[ia] * X[t];
+    if (K) {
+      const int ik = po[i], ak = pv[a];
+      if (ik >= 0 && ak >= 0) v -= (T)K[((int64_t)mm * nok + ik) * nvk + ak];
+    }
+    sig[t] = v;
+  }
+}
+
+void combine_sigma(void* sigma, const void* X, DType t, const double* de64, const float* de32, int m,
+                   int nocc, int nvir, const void* K, DType tk, const int* pos_o, const int* pos_v,
+                   int nok, int nvk, hipStream_t s) {
+  const int64_t total = (int64_t)m * nocc * nvir;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
+  if (t == DType::F64) {
+    RISP_CHECK(tk == DType::F64, RISP_E_ARG, "combine: FP64 sigma needs FP64 exchange");
+    k_combine<double, double, double><<<grid, 256, 0, s>>>((double*)sigma, (const double*)X, de64, m, nocc,
+                                                           nvir, (const double*)K, pos_o, pos_v, nok, nvk);
+  } else {
+    RISP_CHECK(tk == DType::F32, RISP_E_ARG, "combine: FP32 sigma needs FP32 exchange");
+    k_combine<float, float, float><<<grid, 256, 0, s>>>((float*)sigma, (const float*)X, de32, m, nocc, nvir,
+                                                        (const float*)K, pos_o, pos_v, nok, nvk);
+  }
+  RISP_LAUNCHED();
+}
+
+}  // namespace risp

@@ -1,0 +1,45 @@
+// FP64 dense linear algebra on the device for the auxiliary metric, and small data-movement kernels.
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace risp {
+
+// In-place lower Cholesky factor of the SPD matrix A [n][n] (row-major): A = L L^T; the upper
+// triangle is zeroed. Throws RISP_E_ARG if a pivot is not positive.
+void cholesky(double* A, int n, hipStream_t s);
+
+// X = L^-1 for lower-triangular L [n][n]; X is lower triangular.
+void tri_inverse(const double* L, double* X, int n, hipStream_t s);
+
+// out[r][mu] = C[mu][cols[r]] for r < nr (cols may be null: cols[r] = col0 + r); C is [nao][ldc].
+void gather_transpose(const double* C, int64_t ldc, int nao, const int* cols, int col0, int nr,
+                      double* out, hipStream_t s);
+
+// dst[i] = (type) src[i] (FP64/FP32 -> FP64/FP32/BF16), n elements.
+void convert(const void* src, DType ts, void* dst, DType td, int64_t n, hipStream_t s);
+
+// Per-row power-of-two scales s_r = 2^ceil(log2 max_c |A[r][c]|) (1 for a zero row) of an FP64
+// matrix [rows][cols], then dst[r][c] = bf16(A[r][c] / s_r); scale[r] = s_r.
+void scale_rows_bf16(const double* A, int rows, int64_t cols, float* scale, void* dst, hipStream_t s);
+
+// T [P][i][j] -> out [i][P][j]  (element size esz bytes)
+void permute_pij_ipj(const void* T, int nP, int ni, int nj, size_t esz, void* out, hipStream_t s);
+
+// de[i][a] = e[nocc + a] - e[i] (FP64 and FP32 copies)
+void orbital_gaps(const double* e, int nocc, int nvir, double* de64, float* de32, hipStream_t s);
+
+// window position maps: pos[k] = index of k in idx[0..n) or -1 (length len)
+void window_positions(const int* idx, int n, int len, int* pos, hipStream_t s);
+
+// Xw[m][j][b] = X[m][occ[j]][vir[b]] with conversion from ts to td
+void gather_window(const void* X, DType ts, int m, int nocc, int nvir, const int* occ, int nok,
+                   const int* vir, int nvk, void* Xw, DType td, hipStream_t s);
+
+// sigma[m][i][a] += de[i][a] X[m][i][a] - (i, a in window ? K[m][pos_o[i]][pos_v[a]] : 0)
+void combine_sigma(void* sigma, const void* X, DType t, const double* de64, const float* de32, int m,
+                   int nocc, int nvir, const void* K, DType tk, const int* pos_o, const int* pos_v,
+                   int nok, int nvk, hipStream_t s);
+
+}  // namespace risp

@@ -1,0 +1,399 @@
+// C ABI of librisp (declared in include/risp.h): argument checks, status codes, context and
+// factor objects, and the stage entry points used for validation.
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "davidson.hpp"
+#include "factors.hpp"
+#include "integrals.hpp"
+#include "linalg.hpp"
+
+namespace risp {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace risp
+
+using namespace risp;
+
+namespace {
+
+template <typename Fn>
+risp_status guarded(Fn&& fn) {
+  try {
+    set_last_error("");
+    return fn();
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return RISP_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return RISP_E_HIP;
+  } catch (...) {
+    set_last_error("unknown failure");
+    return RISP_E_HIP;
+  }
+}
+
+void use_ctx(const risp_ctx* ctx) {
+  RISP_CHECK(ctx != nullptr, RISP_E_ARG, "context is NULL");
+  RISP_HIP(hipSetDevice(ctx->device));
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct risp_factors_ext {
+  double t_build = 0.0;
+};
+
+extern "C" {
+
+const char* risp_last_error(void) { return g_last_error.c_str(); }
+
+risp_status risp_ctx_create(int32_t device, void* hip_stream, risp_ctx** out) {
+  return guarded([&]() -> risp_status {
+    RISP_CHECK(out != nullptr, RISP_E_ARG, "out is NULL");
+    int ndev = 0;
+    RISP_HIP(hipGetDeviceCount(&ndev));
+    RISP_CHECK(device >= 0 && device < ndev, RISP_E_ARG, "device index out of range");
+    RISP_HIP(hipSetDevice(device));
+    auto* c = new risp_ctx();
+    c->device = device;
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        delete c;
+        throw Error(RISP_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+      }
+      c->own_stream = true;
+    }
+    try {
+      std::vector<double> tab;
+      boys_table_host(tab);
+      c->boys = upload(tab.data(), tab.size(), c->stream);
+      RISP_HIP(hipStreamSynchronize(c->stream));
+    } catch (...) {
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
+      delete c;
+      throw;
+    }
+    *out = c;
+    return RISP_OK;
+  });
+}
+
+risp_status risp_ctx_destroy(risp_ctx* ctx) {
+  return guarded([&]() -> risp_status {
+    if (!ctx) return RISP_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (risp_factors* f : ctx->factors) f->ctx = nullptr;  // factors outlive their context detached
+    ctx->factors.clear();
+    ctx->boys.release();
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return RISP_OK;
+  });
+}
+
+risp_status risp_select_aux(const risp_system* sys, const risp_params* prm, int32_t cap, risp_shell* aux_j,
+                            int32_t* n_j, risp_shell* aux_k, int32_t* n_k) {
+  return guarded([&]() -> risp_status {
+    RISP_CHECK(sys && prm && n_j && n_k, RISP_E_ARG, "NULL argument");
+    RISP_CHECK(sys->natm > 0 && sys->Z && sys->aux_radius, RISP_E_ARG, "atoms, charges and radii are required");
+    RISP_CHECK(prm->theta > 0.0, RISP_E_ARG, "theta must be positive");
+    for (int a = 0; a < sys->natm; ++a)
+      RISP_CHECK(sys->aux_radius[a] > 0.0, RISP_E_ARG, "auxiliary radius must be positive");
+    std::vector<risp_shell> J, K;
+    select_aux(sys, prm, J, K);
+    RISP_CHECK((int)J.size() <= cap && (int)K.size() <= cap, RISP_E_SHAPE, "cap too small for the auxiliary shells");
+    if (aux_j) std::memcpy(aux_j, J.data(), J.size() * sizeof(risp_shell));
+    if (aux_k) std::memcpy(aux_k, K.data(), K.size() * sizeof(risp_shell));
+    *n_j = (int32_t)J.size();
+    *n_k = (int32_t)K.size();
+    return RISP_OK;
+  });
+}
+
+risp_status risp_window(risp_ctx* ctx, int32_t nmo, int32_t nocc, const double* mo_energy, double window_ev,
+                        int32_t window_mode, int32_t* occ_k, int32_t* nocc_k, int32_t* vir_k, int32_t* nvir_k) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(mo_energy && occ_k && nocc_k && vir_k && nvir_k, RISP_E_ARG, "NULL argument");
+    RISP_CHECK(nocc > 0 && nocc < nmo, RISP_E_SHAPE, "need 0 < nocc < nmo");
+    RISP_CHECK(window_mode == RISP_WIN_ABSOLUTE || window_mode == RISP_WIN_FRONTIER, RISP_E_ARG, "bad window_mode");
+    hipStream_t s = ctx->stream;
+    DevBuf e = upload(mo_energy, nmo, s);
+    DevBuf o(nocc * sizeof(int)), v((nmo - nocc) * sizeof(int));
+    int no = 0, nv = 0;
+    window_sets(e.as<double>(), nmo, nocc, window_ev, window_mode, o.as<int>(), &no, v.as<int>(), &nv, s);
+    RISP_HIP(hipMemcpyAsync(occ_k, o.get(), no * sizeof(int), hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipMemcpyAsync(vir_k, v.get(), nv * sizeof(int), hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipStreamSynchronize(s));
+    *nocc_k = no;
+    *nvir_k = nv;
+    return RISP_OK;
+  });
+}
+
+static void check_shells(const risp_system* sys, int naux, const risp_shell* aux) {
+  RISP_CHECK(sys && sys->natm > 0 && sys->coords && sys->nshell > 0 && sys->shells, RISP_E_ARG,
+             "system: atoms and shells are required");
+  RISP_CHECK(naux >= 0 && (naux == 0 || aux), RISP_E_ARG, "auxiliary shells missing");
+  auto chk = [&](const risp_shell& s) {
+    RISP_CHECK(s.l == 0 || s.l == 1, RISP_E_ARG, "only s and p shells are supported");
+    RISP_CHECK(s.atom >= 0 && s.atom < sys->natm, RISP_E_ARG, "shell atom index out of range");
+    RISP_CHECK(s.exponent > 0.0, RISP_E_ARG, "shell exponent must be positive");
+  };
+  for (int k = 0; k < sys->nshell; ++k) chk(sys->shells[k]);
+  for (int k = 0; k < naux; ++k) chk(aux[k]);
+}
+
+risp_status risp_screen(risp_ctx* ctx, const risp_system* sys, int32_t naux_shell, const risp_shell* aux,
+                        double tau, int32_t cap, int32_t* pairs, int32_t* npair) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    check_shells(sys, naux_shell, aux);
+    RISP_CHECK(naux_shell > 0 && npair && tau >= 0.0, RISP_E_ARG, "bad screening arguments");
+    hipStream_t s = ctx->stream;
+    DevShells ao, ax;
+    upload_shells(ao, sys->coords, sys->shells, sys->nshell, s);
+    upload_shells(ax, sys->coords, aux, naux_shell, s);
+    const double qaux = std::sqrt(aux_diag_max(ax, ctx->boys.as<double>(), s));
+    PairList pl;
+    screen_pairs(ao, qaux, tau, true, pl, s);
+    *npair = pl.n;
+    RISP_CHECK(pl.n <= cap, RISP_E_SHAPE, "cap too small for the kept pairs");
+    if (pairs && pl.n > 0) {
+      std::vector<int> a(pl.n), b(pl.n);
+      RISP_HIP(hipMemcpyAsync(a.data(), pl.a.get(), pl.n * sizeof(int), hipMemcpyDeviceToHost, s));
+      RISP_HIP(hipMemcpyAsync(b.data(), pl.b.get(), pl.n * sizeof(int), hipMemcpyDeviceToHost, s));
+      RISP_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < pl.n; ++k) {
+        pairs[2 * k] = a[k];
+        pairs[2 * k + 1] = b[k];
+      }
+    }
+    return RISP_OK;
+  });
+}
+
+risp_status risp_int2c(risp_ctx* ctx, const risp_system* sys, int32_t naux_shell, const risp_shell* aux,
+                       double omega, double* out) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    check_shells(sys, naux_shell, aux);
+    RISP_CHECK(out && naux_shell > 0, RISP_E_ARG, "bad arguments");
+    hipStream_t s = ctx->stream;
+    DevShells ax;
+    upload_shells(ax, sys->coords, aux, naux_shell, s);
+    Operator op;
+    if (omega > 0.0) op = Operator{0.0, 1.0, omega};
+    DevBuf V((size_t)ax.nfunc * ax.nfunc * 8);
+    int2c(ax, op, ctx->boys.as<double>(), V.as<double>(), s);
+    RISP_HIP(hipMemcpyAsync(out, V.get(), V.bytes(), hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipStreamSynchronize(s));
+    return RISP_OK;
+  });
+}
+
+risp_status risp_int3c(risp_ctx* ctx, const risp_system* sys, int32_t naux_shell, const risp_shell* aux,
+                       int32_t aux_begin, int32_t aux_end, double omega, double tau, double* out) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    check_shells(sys, naux_shell, aux);
+    RISP_CHECK(out && naux_shell > 0 && tau >= 0.0, RISP_E_ARG, "bad arguments");
+    RISP_CHECK(0 <= aux_begin && aux_begin < aux_end && aux_end <= naux_shell, RISP_E_ARG, "bad auxiliary range");
+    hipStream_t s = ctx->stream;
+    DevShells ao, ax;
+    upload_shells(ao, sys->coords, sys->shells, sys->nshell, s);
+    upload_shells(ax, sys->coords, aux, naux_shell, s);
+    const double qaux = std::sqrt(aux_diag_max(ax, ctx->boys.as<double>(), s));
+    PairList pl;
+    screen_pairs(ao, qaux, tau, false, pl, s);
+    Operator op;
+    if (omega > 0.0) op = Operator{0.0, 1.0, omega};
+    int nf = 0;
+    for (int k = aux_begin; k < aux_end; ++k) nf += aux[k].l == 0 ? 1 : 3;
+    const size_t n = (size_t)nf * ao.nfunc * ao.nfunc;
+    DevBuf V(n * 8);
+    int3c(ao, pl, ax, aux_begin, aux_end, op, ctx->boys.as<double>(), V.as<double>(), s);
+    RISP_HIP(hipMemcpyAsync(out, V.get(), n * 8, hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipStreamSynchronize(s));
+    return RISP_OK;
+  });
+}
+
+risp_status risp_build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, risp_factors** out) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(out != nullptr, RISP_E_ARG, "out is NULL");
+    auto t0 = std::chrono::steady_clock::now();
+    auto* f = new risp_factors();
+    try {
+      build_factors(ctx, sys, prm, f);
+    } catch (...) {
+      delete f;
+      throw;
+    }
+    f->t_build = seconds_since(t0);
+    ctx->factors.insert(f);
+    *out = f;
+    return RISP_OK;
+  });
+}
+
+risp_status risp_factors_query(const risp_factors* f, risp_factors_desc* d) {
+  return guarded([&]() -> risp_status {
+    RISP_CHECK(f && d, RISP_E_ARG, "NULL argument");
+    std::memset(d, 0, sizeof(*d));
+    d->nao = f->nao;
+    d->nmo = f->nmo;
+    d->nocc = f->nocc;
+    d->nvir = f->nvir;
+    d->naux_j = f->naux_j;
+    d->naux_k = f->naux_k;
+    d->nocc_k = f->nok;
+    d->nvir_k = f->nvk;
+    d->npair = f->npair;
+    d->precision = f->precision;
+    d->bytes = f->bytes();
+    d->t_ia = f->t_ia.get();
+    d->t_ij = f->naux_k ? f->t_ij.get() : nullptr;
+    d->t_ab = f->naux_k ? f->t_ab.get() : nullptr;
+    d->scale_ia = f->precision == RISP_BF16 ? f->scale_ia.as<float>() : nullptr;
+    d->scale_k = (f->precision == RISP_BF16 && f->naux_k) ? f->scale_k.as<float>() : nullptr;
+    d->occ_k = f->occ_k.as<int32_t>();
+    d->vir_k = f->vir_k.as<int32_t>();
+    return RISP_OK;
+  });
+}
+
+risp_status risp_factors_free(risp_factors* f) {
+  return guarded([&]() -> risp_status {
+    if (!f) return RISP_OK;
+    if (f->ctx) {
+      (void)hipSetDevice(f->ctx->device);
+      (void)hipStreamSynchronize(f->ctx->stream);
+      f->ctx->factors.erase(f);
+    }
+    delete f;
+    return RISP_OK;
+  });
+}
+
+risp_status risp_sigma(risp_ctx* ctx, const risp_factors* fc, int32_t m, const void* X_dev, void* sigma_dev,
+                       int32_t dtype) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(fc != nullptr, RISP_E_ARG, "factors are NULL");
+    RISP_CHECK(fc->ctx == ctx, RISP_E_STATE, "factors belong to another context");
+    RISP_CHECK(m >= 0, RISP_E_ARG, "m must be non-negative");
+    RISP_CHECK(m == 0 || (X_dev && sigma_dev), RISP_E_ARG, "NULL device buffer");
+    const int want = fc->precision == RISP_FP64 ? RISP_FP64 : RISP_FP32;
+    RISP_CHECK(dtype == want, RISP_E_ARG,
+               want == RISP_FP64 ? "FP64 factors take FP64 vectors" : "FP32/BF16 factors take FP32 vectors");
+    sigma(const_cast<risp_factors*>(fc), m, X_dev, sigma_dev, false, ctx->stream);
+    return RISP_OK;
+  });
+}
+
+risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_opts* opts, double* energies,
+                          float* vectors, risp_dav_info* info) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(fc && opts && energies, RISP_E_ARG, "NULL argument");
+    RISP_CHECK(fc->ctx == ctx, RISP_E_STATE, "factors belong to another context");
+    risp_factors* f = const_cast<risp_factors*>(fc);
+    const int64_t ov = (int64_t)f->nocc * f->nvir;
+    hipStream_t s = ctx->stream;
+    DavOptions o;
+    o.nstates = opts->nstates;
+    o.block = opts->block;
+    o.max_space = opts->max_space;
+    o.max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
+    o.tol = opts->tol;
+    DevBuf x0;
+    if (opts->nx0 > 0) {
+      RISP_CHECK(opts->x0 != nullptr, RISP_E_ARG, "x0 is NULL");
+      std::vector<double> h((size_t)opts->nx0 * ov);
+      for (size_t t = 0; t < h.size(); ++t) h[t] = (double)opts->x0[t];
+      x0 = upload(h.data(), h.size(), s);
+      RISP_HIP(hipStreamSynchronize(s));
+      o.x0_dev = x0.as<double>();
+      o.nx0 = opts->nx0;
+    }
+    SigmaFn native = [&](int m, const void* X, void* S) { sigma(f, m, X, S, false, s); };
+    const bool correct = f->precision == RISP_BF16 && opts->correction_pass;
+    DavOptions ob = o;
+    if (f->precision == RISP_BF16) {
+      // BF16 products bound the attainable residual: stop at the stage tolerance or on a stall
+      const double bt = opts->bf16_tol > 0.0 ? opts->bf16_tol : 1e-4;
+      if (correct) ob.tol = std::max(o.tol, bt);
+      ob.stall_iters = 6;
+    }
+    DavResult r;
+    davidson(f, ob, native, r);
+    int corr_iters = 0;
+    double t_corr = 0.0;
+    DavResult rc;
+    DavResult* fin = &r;
+    if (correct && r.krows > 0) {
+      // FP32 products from the BF16-converged Ritz vectors: Rayleigh-Ritz, then at most
+      // correction_steps FP32 Davidson steps
+      auto t0 = std::chrono::steady_clock::now();
+      DavOptions oc = o;
+      oc.x0_dev = r.X.as<double>();
+      oc.nx0 = r.krows;
+      oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 3);
+      SigmaFn f32 = [&](int m, const void* X, void* S) { sigma(f, m, X, S, true, s); };
+      davidson(f, oc, f32, rc);
+      corr_iters = rc.iters;
+      t_corr = seconds_since(t0);
+      fin = &rc;
+    }
+    const int ns = std::min<int>(opts->nstates, (int)fin->energies.size());
+    for (int k = 0; k < ns; ++k) energies[k] = fin->energies[k];
+    if (vectors && ns > 0) {
+      std::vector<double> h((size_t)ns * ov);
+      RISP_HIP(hipMemcpyAsync(h.data(), fin->X.get(), h.size() * 8, hipMemcpyDeviceToHost, s));
+      RISP_HIP(hipStreamSynchronize(s));
+      for (size_t t = 0; t < h.size(); ++t) vectors[t] = (float)h[t];
+    }
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->iters = r.iters;
+      info->restarts = r.restarts + rc.restarts;
+      info->sigma_vectors = r.sigma_vectors + rc.sigma_vectors;
+      info->converged = fin->converged ? 1 : 0;
+      info->correction_iters = corr_iters;
+      info->t_build = f->t_build;
+      info->t_sigma = r.t_sigma + rc.t_sigma;
+      info->t_subspace = r.t_subspace + rc.t_subspace;
+      info->t_correct = t_corr;
+      info->sigma_flops = r.sigma_flops + rc.sigma_flops;
+      info->hbm_bytes = f->bytes();
+      // residual history of the main stage followed by that of the correction stage
+      std::vector<double> hist = r.resid_hist;
+      hist.insert(hist.end(), rc.resid_hist.begin(), rc.resid_hist.end());
+      const size_t nh = std::min<size_t>(256, hist.size());
+      for (size_t k = 0; k < nh; ++k) info->resid_hist[k] = hist[k];
+    }
+    if (!fin->converged) {
+      set_last_error("Davidson did not converge within max_iter");
+      return (risp_status)RISP_E_NOTCONV;
+    }
+    return RISP_OK;
+  });
+}
+
+}  // extern "C"

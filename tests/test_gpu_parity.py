@@ -1,0 +1,234 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bit-exact: window index sets and screened pair lists. FP64 integrals: 1e-12 relative. Factors and
+sigma: element by element. Excitation energies: 1e-6 Ha (FP64 / FP32 paths), 2e-5 Ha (BF16 with the
+FP32 correction pass).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrals as OI
+from oracle import risp as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_29257_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def mol0():
+    return synth.make_config0()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    from tests.test_oracle_risp import tiny_molecule
+    return tiny_molecule()
+
+
+@pytest.fixture(scope="module")
+def oracle0(mol0):
+    return R.build_factors(mol0, R.Params())
+
+
+def _params(**kw):
+    import paper_2603_29257_amd as P
+    return P.Params(**kw)
+
+
+# ---------------------------------------------------------------------------------------------
+# stages
+# ---------------------------------------------------------------------------------------------
+def test_window_sets_bit_exact(ctx, mol0):
+    import paper_2603_29257_amd as P
+    cases = [(mol0.mo_energy, mol0.nocc, 40.0)]
+    H2EV = 27.211386245988
+    e = np.array([-2.0, -40.0 / H2EV, -39.0 / H2EV, -0.3, 0.1, 1.0, 40.0 / H2EV, 1.5, 3.0])
+    cases += [(e, 4, 40.0), (e, 4, 0.0), (e, 4, 1e9), (mol0.mo_energy, mol0.nocc, 16.0)]
+    for (ee, no, w) in cases:
+        for mode, name in ((P.WIN_ABSOLUTE, "absolute"), (P.WIN_FRONTIER, "frontier")):
+            o, v = ctx.window(ee, no, w, mode)
+            ro, rv = R.window_sets(ee, no, w, name)
+            assert o.tolist() == ro.tolist() and v.tolist() == rv.tolist(), (w, name)
+
+
+@pytest.mark.parametrize("which", ["tiny", "grid20"])
+def test_screening_bit_exact(ctx, which, tiny, mol0):
+    import paper_2603_29257_amd as P
+    mol = tiny if which == "tiny" else mol0
+    sysc = P.System(mol)
+    auxJ, _ = R.select_aux(mol.Z, mol.aux_radius)
+    for tau in (1e-10, 1e-4, 1e-2):
+        ref, _, ratio = R.schwarz_pairs(mol.coords, mol.shells, auxJ, tau)
+        # margin audit: no pair so close to the threshold that rounding could decide it
+        assert np.min(np.abs(ratio - 1.0)) > 1e-12
+        got = ctx.screen(sysc, auxJ, tau)
+        assert got.shape == ref.shape and np.array_equal(got, ref), tau
+
+
+def test_select_aux_matches_oracle(ctx, mol0):
+    import paper_2603_29257_amd as P
+    J, K = ctx.select_aux(P.System(mol0), _params())
+    rJ, rK = R.select_aux(mol0.Z, mol0.aux_radius)
+    assert J == rJ and K == rK
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.2])
+def test_int2c_fp64(ctx, mol0, omega):
+    import paper_2603_29257_amd as P
+    auxJ, _ = R.select_aux(mol0.Z, mol0.aux_radius)
+    got = ctx.int2c(P.System(mol0), auxJ, omega)
+    ref = OI.int2c(mol0.coords, auxJ, omega if omega > 0 else None)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.2, 1.7])
+def test_int3c_fp64_tiny_all_classes(ctx, tiny, omega):
+    import paper_2603_29257_amd as P
+    auxJ, _ = R.select_aux(tiny.Z, tiny.aux_radius)
+    got = ctx.int3c(P.System(tiny), auxJ, omega=omega)
+    ref = OI.int3c(tiny.coords, tiny.shells, auxJ, omega if omega > 0 else None).transpose(2, 0, 1)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_int3c_fp64_screened_config0(ctx, mol0):
+    import paper_2603_29257_amd as P
+    auxJ, _ = R.select_aux(mol0.Z, mol0.aux_radius)
+    pairs, mask, _ = R.schwarz_pairs(mol0.coords, mol0.shells, auxJ, 1e-10)
+    sel = [0, 1, 7, 22, 23]  # s and p shells at several atoms, a ragged subset
+    got = np.concatenate([ctx.int3c(P.System(mol0), auxJ, k, k + 1, 0.0, 1e-10) for k in sel])
+    ref = OI.int3c(mol0.coords, mol0.shells, auxJ, None, mask, sel).transpose(2, 0, 1)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------------------------
+# factors, sigma, eigenpairs at the 20-atom size
+# ---------------------------------------------------------------------------------------------
+def _gpu_factors(ctx, mol, **kw):
+    import paper_2603_29257_amd as P
+    sysc = P.System(mol)
+    return ctx.build_factors(sysc, _params(**kw))
+
+
+def test_factors_fp64_elementwise(ctx, mol0, oracle0):
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.FP64)
+    assert F.naux_j == oracle0.B_ia.shape[0] and F.naux_k == oracle0.Bx_ij.shape[0]
+    assert F.nocc_k == len(oracle0.occK) and F.nvir_k == len(oracle0.virK)
+    assert F.npair == len(oracle0.pairs)
+    Tia = F.tensor("t_ia").cpu().numpy()
+    Tij = F.tensor("t_ij").cpu().numpy().transpose(1, 0, 2)
+    Tab = F.tensor("t_ab").cpu().numpy()
+    for got, ref, name in ((Tia, oracle0.B_ia, "ia"), (Tij, oracle0.Bx_ij, "ij"), (Tab, oracle0.Bx_ab, "ab")):
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        _print(f"T_{name} FP64 max rel err {err:.3e}")
+        # rounding-order differences (integral algorithm, summation order) of ~1e-14 are amplified by
+        # the metric (sqrt(cond) ~ 1.5e3) and the cancellation of the MO transform (~1e3)
+        assert err <= 5e-8, name
+    assert F.tensor("occ_k").cpu().numpy().tolist() == oracle0.occK.tolist()
+    assert F.tensor("vir_k").cpu().numpy().tolist() == oracle0.virK.tolist()
+    F.free()
+
+
+def test_factors_fp32_and_bf16_storage(ctx, mol0, oracle0):
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.FP32)
+    Tia = F.tensor("t_ia").cpu().numpy().astype(np.float64)
+    err = np.abs(Tia - oracle0.B_ia).max() / np.abs(oracle0.B_ia).max()
+    _print(f"T_ia FP32 max rel err {err:.3e}")
+    assert err <= 1e-6
+    F.free()
+    F = _gpu_factors(ctx, mol0, precision=P.BF16)
+    s = F.tensor("scale_ia").cpu().numpy().astype(np.float64)
+    Tia = F.tensor("t_ia").float().cpu().numpy().astype(np.float64) * s[:, None, None]
+    assert np.all(np.log2(s) == np.round(np.log2(s)))  # powers of two
+    rowmax = np.abs(oracle0.B_ia).reshape(len(s), -1).max(axis=1)
+    assert np.all(s >= rowmax) and np.all(s < 2 * rowmax)
+    err = np.abs(Tia - oracle0.B_ia).max() / np.abs(oracle0.B_ia).max()
+    _print(f"T_ia BF16 max rel err {err:.3e}")
+    assert err <= 2 ** -8
+    F.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("m", [1, 7, 30])
+def test_sigma_matches_oracle(ctx, mol0, oracle0, prec, m):
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
+    X = synth.random_trial_vectors(m, F.nocc, F.nvir, 11)
+    ref = R.sigma(oracle0, X)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Xd = torch.tensor(X, dtype=dt, device=ctx.device)
+    got = ctx.sigma(F, Xd).cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _print(f"sigma {prec} m={m} max rel err {err:.3e}")
+    tol = {"fp64": 1e-9, "fp32": 2e-6, "bf16": 3e-2}[prec]
+    assert err <= tol
+    F.free()
+
+
+def test_sigma_bilinear_symmetry_fp32(ctx, mol0):
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.FP32)
+    X = torch.tensor(synth.random_trial_vectors(3, F.nocc, F.nvir, 1), dtype=torch.float32, device=ctx.device)
+    Y = torch.tensor(synth.random_trial_vectors(3, F.nocc, F.nvir, 2), dtype=torch.float32, device=ctx.device)
+    a = (Y.double() * ctx.sigma(F, X).double()).sum(dim=(1, 2))
+    b = (X.double() * ctx.sigma(F, Y).double()).sum(dim=(1, 2))
+    assert torch.max(torch.abs(a - b)).item() <= 1e-6
+    F.free()
+
+
+@pytest.mark.parametrize("prec,tol_e", [("fp64", 1e-6), ("fp32", 1e-6), ("bf16", 2e-5)])
+def test_davidson_energies_config0(ctx, mol0, oracle0, prec, tol_e):
+    import paper_2603_29257_amd as P
+    w, U = R.lowest_eigh(R.dense_A(oracle0), 5)
+    F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
+    e, vec, info = ctx.davidson(F, 5, tol=1e-6 if prec == "fp64" else 1e-5)
+    _print(f"davidson {prec}: iters {info.iters} restarts {info.restarts} corr {info.correction_iters} "
+           f"max |dE| {np.abs(e - w).max():.3e}")
+    assert info.converged
+    assert np.abs(e - w).max() <= tol_e
+    for k in range(5):
+        gap = min(abs(w[k] - w[j]) for j in range(5) if j != k)
+        if gap >= 1e-4:
+            assert abs(abs(np.dot(vec[k].astype(np.float64), U[k])) - 1.0) <= 1e-4
+    F.free()
+
+
+def test_davidson_restart_same_answer(ctx, mol0, oracle0):
+    import paper_2603_29257_amd as P
+    w, _ = R.lowest_eigh(R.dense_A(oracle0), 5)
+    F = _gpu_factors(ctx, mol0, precision=P.FP64)
+    e, _, info = ctx.davidson(F, 5, tol=1e-7, max_space=30)
+    assert info.converged and info.restarts > 0
+    assert np.abs(e - w).max() <= 1e-8
+    F.free()
+
+
+def test_errors_are_reported(ctx, mol0):
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.FP32)
+    with pytest.raises(ValueError):
+        ctx.sigma(F, torch.zeros((2, 3, 4), device=ctx.device))
+    with pytest.raises(P.RispError):
+        ctx.davidson(F, 0)
+    F.free()
+    bad = synth.make_config0()
+    bad.nocc = bad.mo_coeff.shape[1]
+    with pytest.raises(P.RispError):
+        _gpu_factors(ctx, bad)
