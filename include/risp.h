@@ -99,7 +99,8 @@ typedef struct {
   int32_t max_iter;        /* 0 = 200 */
   double tol;              /* residual 2-norm convergence threshold per state */
   int32_t correction_pass; /* BF16 factors: refine the BF16-converged vectors with FP32 products */
-  int32_t correction_steps;/* FP32 Davidson steps after the FP32 Rayleigh-Ritz; 0 = 3 */
+  int32_t correction_steps;/* at most this many FP32 Davidson steps after the FP32 Rayleigh-Ritz;
+                              0 = 8 */
   double bf16_tol;         /* BF16 stage stops at max(tol, bf16_tol) or when its residual stalls;
                               0 = 1e-4 */
   int32_t nx0;             /* optional initial vectors (resume): count, 0 = unit-vector guess */
@@ -108,12 +109,16 @@ typedef struct {
 } risp_dav_opts;
 
 typedef struct {
-  int32_t iters, restarts, sigma_vectors, converged;
-  int32_t correction_iters, reserved;
-  double t_build, t_sigma, t_subspace, t_correct; /* seconds */
-  double sigma_flops;                              /* algorithmic flops of all sigma blocks */
-  int64_t hbm_bytes;                               /* device bytes held by the factors */
-  double resid_hist[256];                          /* max residual norm per iteration */
+  int32_t iters, restarts, sigma_vectors, converged; /* main stage (BF16 stage for BF16 factors) */
+  int32_t correction_iters, correction_vectors;       /* FP32 correction stage */
+  double t_build;                  /* seconds in risp_build_factors for these factors */
+  double t_sigma, t_subspace;      /* main stage: sigma blocks and subspace work (seconds) */
+  double t_correct;                /* correction stage, all of it (seconds) */
+  double t_sigma_correct;          /* correction stage sigma blocks (seconds) */
+  double sigma_flops;              /* algorithmic flops of the main-stage sigma blocks */
+  double sigma_flops_correct;      /* algorithmic flops of the correction-stage sigma blocks */
+  int64_t hbm_bytes;               /* device bytes held by the factors */
+  double resid_hist[256];          /* max residual norm per iteration (main, then correction) */
 } risp_dav_info;
 
 typedef struct {
@@ -133,6 +138,22 @@ typedef struct {
   const int32_t *vir_k;   /* dev [nvir_k] window virtual indices (0-based in the virtual space) */
 } risp_factors_desc;
 
+/* Per-phase timing of sigma products (HIP events on the context stream around each launch). */
+enum {
+  RISP_PHASE_COULOMB_Y = 0, /* Y[P][m] = sum_ia T_ia^P X_mia (split-K product and its reduction) */
+  RISP_PHASE_COULOMB_J = 1, /* sigma_mia = 2 sum_P Y[P][m] T_ia^P */
+  RISP_PHASE_EXCHANGE_M = 2,/* M^P_mja = sum_b T_ab^P X_mjb, one launch per auxiliary chunk */
+  RISP_PHASE_EXCHANGE_K = 3,/* K_mia += sum_(P, j) T_ij^P M^P_mja, one launch per auxiliary chunk */
+  RISP_PHASE_OTHER = 4,     /* window gather, conversions, diagonal term and combine */
+  RISP_NPHASE = 5
+};
+typedef struct {
+  int64_t launches; /* timed launches (or launch groups) */
+  double ms;        /* summed event time */
+  double flops;     /* algorithmic flops of those launches */
+  double bytes;     /* algorithmic HBM bytes (each operand read once, each result written once) */
+} risp_phase_stat;
+
 typedef struct risp_ctx risp_ctx;
 typedef struct risp_factors risp_factors;
 
@@ -143,6 +164,10 @@ const char *risp_last_error(void);
  * a stream owned by the context. */
 risp_status risp_ctx_create(int32_t device, void *hip_stream, risp_ctx **out);
 risp_status risp_ctx_destroy(risp_ctx *ctx);
+
+/* Enable (1) or disable (0) sigma phase timing; reset != 0 clears the counters. If out is not
+ * NULL it receives RISP_NPHASE entries (the stream is synchronised first). */
+risp_status risp_ctx_profile(risp_ctx *ctx, int32_t enable, int32_t reset, risp_phase_stat *out);
 
 /* ---- stages of the factor build (exposed for validation; risp_build_factors runs them all) ---- */
 

@@ -252,11 +252,11 @@ def sigma(F: Factors, X: np.ndarray) -> np.ndarray:
     Y = Bf @ X.reshape(m, o * v).T  # [P, m]
     out += 2.0 * (Y.T @ Bf).reshape(m, o, v)
     if F.Bx_ij.shape[0]:
-        Xw = X[:, F.occK][:, :, F.virK]  # [m, noK, nvK]
+        Xw = np.ascontiguousarray(X[:, F.occK][:, :, F.virK])  # [m, noK, nvK] (contiguous for BLAS)
         K = np.zeros_like(Xw)
         for P in range(F.Bx_ij.shape[0]):
             M = Xw @ F.Bx_ab[P]  # M^P_mja = sum_b Xw_mjb Bx^P_ba (Bx^P_ab is symmetric in a, b)
-            K += np.einsum("ij,mja->mia", F.Bx_ij[P], M)
+            K += F.Bx_ij[P] @ M  # K_mia += sum_j Bx^P_ij M^P_mja (matmul broadcast over m)
         out[np.ix_(np.arange(m), F.occK, F.virK)] -= K
     return out
 

@@ -24,7 +24,7 @@ RSH_COMBINED, RSH_SPLIT = 0, 1
 WIN_ABSOLUTE, WIN_FRONTIER = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
-EXPORTS = ("risp_last_error", "risp_ctx_create", "risp_ctx_destroy", "risp_select_aux", "risp_window",
+EXPORTS = ("risp_last_error", "risp_ctx_create", "risp_ctx_destroy", "risp_ctx_profile", "risp_select_aux", "risp_window",
            "risp_screen", "risp_int2c", "risp_int3c", "risp_build_factors", "risp_factors_query",
            "risp_factors_free", "risp_sigma", "risp_davidson")
 
@@ -62,10 +62,17 @@ class DavOptsC(C.Structure):
 
 class DavInfoC(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("sigma_vectors", C.c_int32),
-                ("converged", C.c_int32), ("correction_iters", C.c_int32), ("reserved", C.c_int32),
+                ("converged", C.c_int32), ("correction_iters", C.c_int32), ("correction_vectors", C.c_int32),
                 ("t_build", C.c_double), ("t_sigma", C.c_double), ("t_subspace", C.c_double),
-                ("t_correct", C.c_double), ("sigma_flops", C.c_double), ("hbm_bytes", C.c_int64),
-                ("resid_hist", C.c_double * 256)]
+                ("t_correct", C.c_double), ("t_sigma_correct", C.c_double), ("sigma_flops", C.c_double),
+                ("sigma_flops_correct", C.c_double), ("hbm_bytes", C.c_int64), ("resid_hist", C.c_double * 256)]
+
+
+class PhaseStatC(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+PHASES = ("coulomb_y", "coulomb_j", "exchange_m", "exchange_k", "other")
 
 
 class FactorsDescC(C.Structure):
@@ -86,6 +93,7 @@ def load_library(path: str = LIBPATH):
     sigs = {
         "risp_ctx_create": [i32, vp, P(vp)],
         "risp_ctx_destroy": [vp],
+        "risp_ctx_profile": [vp, i32, i32, P(PhaseStatC)],
         "risp_select_aux": [P(SystemC), P(ParamsC), i32, P(Shell), P(i32), P(Shell), P(i32)],
         "risp_window": [vp, i32, i32, P(dbl), dbl, i32, P(i32), P(i32), P(i32), P(i32)],
         "risp_screen": [vp, P(SystemC), i32, P(Shell), dbl, i32, P(i32), P(i32)],
@@ -175,11 +183,14 @@ class DavInfo:
     sigma_vectors: int
     converged: bool
     correction_iters: int
+    correction_vectors: int
     t_build: float
     t_sigma: float
     t_subspace: float
     t_correct: float
+    t_sigma_correct: float
     sigma_flops: float
+    sigma_flops_correct: float
     hbm_bytes: int
     resid_hist: list
 
@@ -266,6 +277,13 @@ class Context:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    def profile(self, enable=True, reset=False):
+        """Switch sigma phase timing; returns the counters accumulated so far as a dict."""
+        arr = (PhaseStatC * len(PHASES))()
+        _check(_LIB.risp_ctx_profile(self.handle, int(enable), int(reset), arr))
+        return {name: dict(launches=arr[k].launches, ms=arr[k].ms, flops=arr[k].flops, bytes=arr[k].bytes)
+                for k, name in enumerate(PHASES)}
 
     # ---- stages ----
     def select_aux(self, sys: System, prm: Params):
@@ -357,6 +375,7 @@ class Context:
             _check(rc)
         n = min(256, info.iters + info.correction_iters)
         di = DavInfo(info.iters, info.restarts, info.sigma_vectors, bool(info.converged), info.correction_iters,
-                     info.t_build, info.t_sigma, info.t_subspace, info.t_correct, info.sigma_flops,
-                     info.hbm_bytes, list(info.resid_hist[:n]))
+                     info.correction_vectors, info.t_build, info.t_sigma, info.t_subspace, info.t_correct,
+                     info.t_sigma_correct, info.sigma_flops, info.sigma_flops_correct, info.hbm_bytes,
+                     list(info.resid_hist[:n]))
         return e, vec, di

@@ -2,6 +2,7 @@
 // transforms, metric application, storage precision) and the sigma product A X.
 #include <algorithm>
 #include <cmath>
+#include <optional>
 
 #include "factors.hpp"
 #include "linalg.hpp"
@@ -14,7 +15,44 @@ int64_t risp_factors::bytes() const {
                    ws_k.bytes() + ws_split.bytes());
 }
 
+void risp_ctx::resolve_phases() {
+  for (auto& p : phase) {
+    for (auto& ev : p.pending) {
+      float ms = 0.f;
+      RISP_HIP(hipEventSynchronize(ev.second));
+      RISP_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
+      p.ms += ms;
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    p.pending.clear();
+  }
+}
+
+void risp_ctx::clear_phases() {
+  resolve_phases();
+  for (auto& p : phase) p = risp::PhaseLog();
+}
+
 namespace risp {
+
+PhaseScope::PhaseScope(risp_ctx* c, int ph, double flops, double bytes) : c_(c), ph_(ph) {
+  if (!c_->profiling) return;
+  RISP_HIP(hipEventCreate(&a_));
+  RISP_HIP(hipEventRecord(a_, c_->stream));
+  PhaseLog& p = c_->phase[ph_];
+  p.launches += 1;
+  p.flops += flops;
+  p.bytes += bytes;
+}
+
+PhaseScope::~PhaseScope() noexcept(false) {
+  if (!a_) return;
+  hipEvent_t b = nullptr;
+  RISP_HIP(hipEventCreate(&b));
+  RISP_HIP(hipEventRecord(b, c_->stream));
+  c_->phase[ph_].pending.emplace_back(a_, b);
+}
 
 void validate_system(const risp_system* sys) {
   RISP_CHECK(sys != nullptr, RISP_E_ARG, "system is NULL");
@@ -391,11 +429,15 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   // Coulomb pass 1: Y[P][m] = s_P^2 sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
   const void* Xc = X;
   if (bf) {
+    PhaseScope po(f->ctx, RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
     convert(X, DType::F32, f->ws_xbf.get(), DType::BF16, m * ov, s);
     Xc = f->ws_xbf.get();
   }
   const float* rs = bf ? f->scale_ia2.as<float>() : nullptr;  // s_P^2 folded into Y (exact)
+  const size_t esz = dtype_size(tc);
   {
+    PhaseScope ps(f->ctx, RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * m,
+                  (double)esz * ((double)nJ * ov + (double)m * ov) + 4.0 * nJ * m);
     Gemm g;
     g.M = nJ;
     g.N = m;
@@ -418,9 +460,12 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   {
     const void* Yc = f->ws_y.get();
     if (bf) {
+      PhaseScope po(f->ctx, RISP_PHASE_OTHER, 0.0, 6.0 * nJ * m);
       convert(f->ws_y.get(), DType::F32, f->ws_ybf.get(), DType::BF16, (int64_t)nJ * m, s);
       Yc = f->ws_ybf.get();
     }
+    PhaseScope ps(f->ctx, RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * m,
+                  (double)esz * ((double)nJ * ov + (double)nJ * m) + (double)dtype_size(tv) * m * ov);
     Gemm g;
     g.M = m;
     g.N = (int)ov;
@@ -442,8 +487,12 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   const int nK = f->naux_k, nok = f->nok, nvk = f->nvk;
   const bool exch = nK > 0 && nok > 0 && nvk > 0;
   if (exch) {
-    gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
-                  f->ws_xw.get(), tc, s);
+    {
+      PhaseScope po(f->ctx, RISP_PHASE_OTHER, 0.0,
+                    (double)m * nok * nvk * (dtype_size(tv) + dtype_size(tc)));
+      gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
+                    f->ws_xw.get(), tc, s);
+    }
     const size_t csz = dtype_size(tc);
     const int64_t per_p = (int64_t)m * nvk * nok;
     const int pc = (int)std::min<int64_t>(nK, f->ws_mt.bytes() / (per_p * csz));
@@ -453,6 +502,10 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
     for (int P0 = 0; P0 < nK; P0 += pc) {
       const int np = std::min(pc, nK - P0);
       // GEMM1: Mt[m][a][(p, j)] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]
+      std::optional<PhaseScope> ps1(std::in_place, f->ctx, RISP_PHASE_EXCHANGE_M,
+                                    2.0 * m * np * (double)nvk * nvk * nok,
+                                    (double)csz * ((double)np * nvk * nvk + (double)m * nok * nvk +
+                                                   (double)m * np * nvk * nok));
       Gemm g1;
       g1.M = nvk;
       g1.N = nok;
@@ -475,7 +528,11 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g1.sc2 = nok;
       g1.batch_scale = bf ? f->scale_k.as<float>() + P0 : nullptr;
       gemm(g1, nullptr, s);
+      ps1.reset();
       // GEMM2: K[m][i][a] += sum_(p, j) T_ij[i][(P0 + p) j] Mt[m][a][(p, j)]
+      PhaseScope ps2(f->ctx, RISP_PHASE_EXCHANGE_K, 2.0 * m * (double)nok * np * nok * nvk,
+                     (double)csz * ((double)nok * np * nok + (double)m * np * nvk * nok) +
+                         (double)dtype_size(tacc) * m * nok * nvk * (P0 > 0 ? 2.0 : 1.0));
       Gemm g2;
       g2.M = nok;
       g2.N = nvk;
@@ -495,6 +552,8 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       gemm(g2, nullptr, s);
     }
   }
+  PhaseScope po(f->ctx, RISP_PHASE_OTHER, (double)m * ov * 3.0,
+                (double)m * ov * dtype_size(tv) * 3.0 + (double)m * nok * nvk * dtype_size(tacc));
   combine_sigma(sig, X, tv, f->de64.as<double>(), f->de32.as<float>(), m, f->nocc, f->nvir,
                 exch ? f->ws_k.get() : nullptr, tacc, f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk, s);
 }

@@ -9,13 +9,40 @@
 
 struct risp_factors;
 
+namespace risp {
+// Event-timed launches of one sigma phase.
+struct PhaseLog {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  int64_t launches = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+}  // namespace risp
+
 struct risp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   risp::DevBuf boys;                // Boys-function Taylor table
   std::set<risp_factors*> factors;  // live factor objects (detached when the context goes away)
+  bool profiling = false;
+  risp::PhaseLog phase[RISP_NPHASE];
+  void resolve_phases();  // fold pending events into ms (synchronises)
+  void clear_phases();
 };
+
+namespace risp {
+// Records HIP events around the launches issued during its lifetime when profiling is on.
+class PhaseScope {
+ public:
+  PhaseScope(risp_ctx* c, int ph, double flops, double bytes);
+  ~PhaseScope() noexcept(false);
+
+ private:
+  risp_ctx* c_;
+  int ph_;
+  hipEvent_t a_ = nullptr;
+};
+}  // namespace risp
 
 struct risp_factors {
   risp_ctx* ctx = nullptr;

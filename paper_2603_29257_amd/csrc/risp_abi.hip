@@ -96,11 +96,34 @@ risp_status risp_ctx_destroy(risp_ctx* ctx) {
     if (!ctx) return RISP_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    try {
+      ctx->clear_phases();
+    } catch (...) {
+    }
     for (risp_factors* f : ctx->factors) f->ctx = nullptr;  // factors outlive their context detached
     ctx->factors.clear();
     ctx->boys.release();
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+    return RISP_OK;
+  });
+}
+
+risp_status risp_ctx_profile(risp_ctx* ctx, int32_t enable, int32_t reset, risp_phase_stat* out) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->resolve_phases();
+    if (out) {
+      for (int p = 0; p < RISP_NPHASE; ++p) {
+        out[p].launches = ctx->phase[p].launches;
+        out[p].ms = ctx->phase[p].ms;
+        out[p].flops = ctx->phase[p].flops;
+        out[p].bytes = ctx->phase[p].bytes;
+      }
+    }
+    if (reset) ctx->clear_phases();
+    ctx->profiling = enable != 0;
     return RISP_OK;
   });
 }
@@ -339,7 +362,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       // BF16 products bound the attainable residual: stop at the stage tolerance or on a stall
       const double bt = opts->bf16_tol > 0.0 ? opts->bf16_tol : 1e-4;
       if (correct) ob.tol = std::max(o.tol, bt);
-      ob.stall_iters = 6;
+      ob.stall_iters = 3;
     }
     DavResult r;
     davidson(f, ob, native, r);
@@ -354,7 +377,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       DavOptions oc = o;
       oc.x0_dev = r.X.as<double>();
       oc.nx0 = r.krows;
-      oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 3);
+      oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 8);
       SigmaFn f32 = [&](int m, const void* X, void* S) { sigma(f, m, X, S, true, s); };
       davidson(f, oc, f32, rc);
       corr_iters = rc.iters;
@@ -373,14 +396,17 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       std::memset(info, 0, sizeof(*info));
       info->iters = r.iters;
       info->restarts = r.restarts + rc.restarts;
-      info->sigma_vectors = r.sigma_vectors + rc.sigma_vectors;
+      info->sigma_vectors = r.sigma_vectors;
       info->converged = fin->converged ? 1 : 0;
       info->correction_iters = corr_iters;
+      info->correction_vectors = rc.sigma_vectors;
       info->t_build = f->t_build;
-      info->t_sigma = r.t_sigma + rc.t_sigma;
-      info->t_subspace = r.t_subspace + rc.t_subspace;
+      info->t_sigma = r.t_sigma;
+      info->t_subspace = r.t_subspace;
       info->t_correct = t_corr;
-      info->sigma_flops = r.sigma_flops + rc.sigma_flops;
+      info->t_sigma_correct = rc.t_sigma;
+      info->sigma_flops = r.sigma_flops;
+      info->sigma_flops_correct = rc.sigma_flops;
       info->hbm_bytes = f->bytes();
       // residual history of the main stage followed by that of the correction stage
       std::vector<double> hist = r.resid_hist;
