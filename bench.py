@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-aux", type=int, default=48, help="exchange auxiliary slices in the CPU sample")
+    ap.add_argument("--no-serving", action="store_true", help="skip the 64-job serving stream")
+    ap.add_argument("--serving-jobs", type=int, default=64)
     return ap.parse_args()
 
 
@@ -77,6 +79,85 @@ def cpu_baseline(mol, nsample_k, m=30, repeat=1):
             "seconds": dt, "flops": flops}
 
 
+def _gen_k(item):
+    k, (n, seed) = item
+    sys.path.insert(0, ROOT)
+    import synth
+    return k, synth.make_chain_ring(int(n), int(seed))
+
+
+def serving_jobs(n_jobs=64, seed=2603, mean_gap=0.5, workers=8):
+    """The serving stream: sizes U{50..400} atoms (C:H = 3:2), nstates U{5..15}, FP32/BF16 half and
+    half in a seeded order, exponential inter-arrival gaps (Poisson arrivals); job k's molecule uses
+    seed 2603 * 1000 + k."""
+    import multiprocessing as mp
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(50, 401, n_jobs)
+    nstates = rng.integers(5, 16, n_jobs)
+    prec = rng.permutation(np.arange(n_jobs) % 2)
+    gaps = rng.exponential(mean_gap, n_jobs)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    # fresh worker interpreters (forking a process whose BLAS threads are running can deadlock),
+    # two BLAS threads each
+    saved = os.environ.get("OPENBLAS_NUM_THREADS")
+    os.environ["OPENBLAS_NUM_THREADS"] = "2"
+    mols = [None] * n_jobs
+    try:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            args = [(int(n), seed * 1000 + k) for k, n in enumerate(sizes)]
+            for done, (k, m) in enumerate(pool.imap_unordered(_gen_k, list(enumerate(args)))):
+                mols[k] = m
+                if done % 8 == 7:
+                    print(f"# serving molecules {done + 1}/{n_jobs}", file=sys.stderr, flush=True)
+    finally:
+        if saved is None:
+            os.environ.pop("OPENBLAS_NUM_THREADS", None)
+        else:
+            os.environ["OPENBLAS_NUM_THREADS"] = saved
+    return [dict(mol=m, nstates=int(ns), prec=("fp32", "bf16")[int(p)], arrival=float(a))
+            for m, ns, p, a in zip(mols, nstates, prec, arrivals)]
+
+
+def serving_bench(jobs, tol=1e-5, max_active=8):
+    """Submit the jobs at their arrival times, poll until all are done; latency = done - submit."""
+    import numpy as np
+
+    import paper_2603_29257_amd as P
+    ctx = P.Context(0)
+    ctx.serve_config(0, max_active=max_active, use_graphs=True)
+    systems = [P.System(j["mol"]) for j in jobs]
+    ids, pending = [], {}
+    t0 = time.perf_counter()
+    k = 0
+    results = {}
+    while len(results) < len(jobs):
+        now = time.perf_counter() - t0
+        while k < len(jobs) and jobs[k]["arrival"] <= now:
+            jid = ctx.submit(systems[k], P.Params(precision=P.PRECISIONS[jobs[k]["prec"]]), jobs[k]["nstates"], tol=tol)
+            ids.append(jid)
+            pending[jid] = k
+            k += 1
+        for jid in list(pending):
+            r = ctx.poll(jid, jobs[pending[jid]]["nstates"])
+            if r is not None:
+                results[pending.pop(jid)] = r
+                if len(results) % 8 == 0:
+                    print(f"# serving {len(results)}/{len(jobs)} done at {time.perf_counter() - t0:.1f} s",
+                          file=sys.stderr, flush=True)
+        time.sleep(0.005)
+    stats = ctx.serve_stats()
+    ctx.close()
+    lat = np.array([results[i]["t_done"] - results[i]["t_submit"] for i in range(len(jobs))])
+    makespan = max(r["t_done"] for r in results.values()) - min(r["t_submit"] for r in results.values())
+    ok = all(r["status"] == 0 for r in results.values())
+    return {"jobs": len(jobs), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "makespan_s": float(makespan), "jobs_per_hour": len(jobs) / makespan * 3600,
+            "all_converged": ok, "graph_ticks": stats["graph_ticks"], "ticks": stats["ticks"],
+            "max_active": max_active, "mean_gap_s": 0.5}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -91,6 +172,7 @@ def main():
 
     t_gen = time.perf_counter()
     mol = synth.config_system(args.workload)
+    jobs = None if args.no_serving else serving_jobs(args.serving_jobs)
     t_gen = time.perf_counter() - t_gen
     ctx = P.Context(0)
     sysc = P.System(mol)
@@ -167,7 +249,7 @@ def main():
                             "correction": res[p]["t_correct"]} for p in res},
         "phases_bf16": phases,
         "roofline": roofline,
-        "latency": None,
+        "latency": None if jobs is None else serving_bench(jobs, tol=args.tol),
         "generator_s": t_gen,
     }
     if "fp32" in res:

@@ -232,6 +232,51 @@ risp_status risp_sigma(risp_ctx *ctx, const risp_factors *f, int32_t m, const vo
 risp_status risp_davidson(risp_ctx *ctx, const risp_factors *f, const risp_dav_opts *opts,
                           double *energies, float *vectors, risp_dav_info *info);
 
+/* ---- serving: continuous batching of excitation jobs ---- */
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* device bytes the resident jobs may use; 0 = 85 % of the free memory
+                               when serving starts */
+  int32_t max_active;       /* jobs resident at once; 0 = 8 */
+  int32_t use_graphs;       /* 1: each tick's sigma blocks are captured and launched as one hipGraph */
+} risp_serve_opts;
+
+typedef struct {
+  int32_t status;     /* the job's own status: RISP_OK, RISP_E_NOTCONV or an error code */
+  int32_t nstates;    /* energies written */
+  double *energies;   /* caller buffer [nstates] or NULL */
+  float *vectors;     /* caller buffer [nstates][nocc*nvir] or NULL */
+  risp_dav_info info;
+  double t_submit, t_admit, t_first_sigma, t_done; /* seconds since serving started */
+  char message[256];  /* error text when status < 0 */
+} risp_result;
+
+typedef struct {
+  int32_t queued, active, done, reserved;
+  int64_t budget_bytes, used_bytes;
+  int64_t ticks, graph_ticks;
+} risp_serve_stats;
+
+/* Configure serving before the first submit (RISP_E_STATE afterwards). */
+risp_status risp_serve_config(risp_ctx *ctx, const risp_serve_opts *opts);
+
+/* Estimated device footprint of a job (host-only computation; the admission rule uses it). */
+risp_status risp_job_footprint(const risp_system *sys, const risp_params *prm, const risp_dav_opts *opts,
+                               int64_t *bytes);
+
+/* Queue a job: the inputs are deep-copied (the caller may free them at once). A job that does not
+ * fit the free budget waits in the queue; one larger than the whole budget is rejected with
+ * RISP_E_NOMEM. opts->x0 is not supported here. Thread-safe. */
+risp_status risp_submit(risp_ctx *ctx, const risp_system *sys, const risp_params *prm,
+                        const risp_dav_opts *opts, uint64_t *job_id);
+
+/* RISP_PENDING while the job is queued or running; RISP_OK once finished, with out filled (the
+ * job's own outcome in out->status) and the job released; RISP_E_NOTFOUND for an unknown or already
+ * polled id. Thread-safe. */
+risp_status risp_poll(risp_ctx *ctx, uint64_t job_id, risp_result *out);
+
+risp_status risp_serve_stats_get(risp_ctx *ctx, risp_serve_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

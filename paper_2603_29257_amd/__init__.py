@@ -6,7 +6,7 @@ loaded on first use of a name below, so the build module imports without the lib
 """
 _EXPORTS = ("BF16", "FP32", "FP64", "PRECISIONS", "RSH_COMBINED", "RSH_SPLIT", "WIN_ABSOLUTE",
             "WIN_FRONTIER", "Context", "DavInfo", "Factors", "Params", "RispError", "System", "load_library",
-            "PHASES")
+            "PHASES", "job_footprint")
 
 
 def __getattr__(name):

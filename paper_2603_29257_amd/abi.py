@@ -26,7 +26,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 EXPORTS = ("risp_last_error", "risp_ctx_create", "risp_ctx_destroy", "risp_ctx_profile", "risp_select_aux", "risp_window",
            "risp_screen", "risp_int2c", "risp_int3c", "risp_build_factors", "risp_factors_query",
-           "risp_factors_free", "risp_sigma", "risp_davidson")
+           "risp_factors_free", "risp_sigma", "risp_davidson", "risp_serve_config", "risp_job_footprint",
+           "risp_submit", "risp_poll", "risp_serve_stats_get")
 
 
 class RispError(RuntimeError):
@@ -83,6 +84,23 @@ class FactorsDescC(C.Structure):
                 ("scale_k", C.c_void_p), ("occ_k", C.c_void_p), ("vir_k", C.c_void_p)]
 
 
+class ServeOptsC(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_active", C.c_int32), ("use_graphs", C.c_int32)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("nstates", C.c_int32), ("energies", C.POINTER(C.c_double)),
+                ("vectors", C.POINTER(C.c_float)), ("info", DavInfoC), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_first_sigma", C.c_double), ("t_done", C.c_double),
+                ("message", C.c_char * 256)]
+
+
+class ServeStatsC(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("active", C.c_int32), ("done", C.c_int32), ("reserved", C.c_int32),
+                ("budget_bytes", C.c_int64), ("used_bytes", C.c_int64), ("ticks", C.c_int64),
+                ("graph_ticks", C.c_int64)]
+
+
 def load_library(path: str = LIBPATH):
     if not os.path.exists(path):
         raise ImportError(f"librisp.so not built at {path}: run paper_2603_29257_amd.build.build()")
@@ -104,6 +122,11 @@ def load_library(path: str = LIBPATH):
         "risp_factors_free": [vp],
         "risp_sigma": [vp, vp, i32, vp, vp, i32],
         "risp_davidson": [vp, vp, P(DavOptsC), P(dbl), P(C.c_float), P(DavInfoC)],
+        "risp_serve_config": [vp, P(ServeOptsC)],
+        "risp_job_footprint": [P(SystemC), P(ParamsC), P(DavOptsC), P(C.c_int64)],
+        "risp_submit": [vp, P(SystemC), P(ParamsC), P(DavOptsC), P(C.c_uint64)],
+        "risp_poll": [vp, C.c_uint64, P(ResultC)],
+        "risp_serve_stats_get": [vp, P(ServeStatsC)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -238,6 +261,15 @@ class Factors:
         return out
 
 
+def job_footprint(sys: System, prm: Params, nstates=15, block=0, max_space=0):
+    """Device bytes the admission rule reserves for a job (host-side estimate)."""
+    o = DavOptsC(nstates, block, max_space, 0, 1e-5, 1, 0, 0.0, 0, 0, None)
+    p = prm.c()
+    out = C.c_int64()
+    _check(_LIB.risp_job_footprint(C.byref(sys.c), C.byref(p), C.byref(o), C.byref(out)))
+    return out.value
+
+
 def _memcpy_d2d(dst, src, nbytes):
     import torch
     # a raw device-to-device copy through a tensor view of the source
@@ -355,6 +387,44 @@ class Context:
         X.record_stream(self.stream)
         out.record_stream(self.stream)
         return out
+
+    # ---- serving ----
+    def serve_config(self, budget_bytes=0, max_active=0, use_graphs=True):
+        o = ServeOptsC(int(budget_bytes), int(max_active), int(use_graphs))
+        _check(_LIB.risp_serve_config(self.handle, C.byref(o)))
+
+    def submit(self, sys: System, prm: Params, nstates, tol=1e-5, block=0, max_space=0, max_iter=0,
+               correction_pass=True, correction_steps=0, bf16_tol=0.0):
+        o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
+                     0, 0, None)
+        p = prm.c()
+        jid = C.c_uint64()
+        _check(_LIB.risp_submit(self.handle, C.byref(sys.c), C.byref(p), C.byref(o), C.byref(jid)))
+        return jid.value
+
+    def poll(self, job_id, nstates, ov=None):
+        """None while pending; else a dict with the job's status, energies, vectors and timestamps."""
+        e = np.zeros(nstates)
+        vec = np.zeros((nstates, ov), np.float32) if ov else None
+        r = ResultC()
+        r.energies = _ptr(e, C.c_double)
+        r.vectors = _ptr(vec, C.c_float) if vec is not None else None
+        rc = _LIB.risp_poll(self.handle, C.c_uint64(job_id), C.byref(r))
+        if rc == RISP_PENDING:
+            return None
+        _check(rc)
+        info = r.info
+        n = min(256, info.iters + info.correction_iters)
+        return dict(status=r.status, energies=e[:r.nstates], vectors=None if vec is None else vec[:r.nstates],
+                    t_submit=r.t_submit, t_admit=r.t_admit, t_first_sigma=r.t_first_sigma, t_done=r.t_done,
+                    message=r.message.decode(), iters=info.iters, correction_iters=info.correction_iters,
+                    converged=bool(info.converged), sigma_flops=info.sigma_flops + info.sigma_flops_correct,
+                    t_build=info.t_build, resid_hist=list(info.resid_hist[:n]))
+
+    def serve_stats(self):
+        st = ServeStatsC()
+        _check(_LIB.risp_serve_stats_get(self.handle, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServeStatsC._fields_ if k != "reserved"}
 
     def davidson(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, correction_pass=True,
                  x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0):

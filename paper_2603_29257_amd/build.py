@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librisp.so")
-SOURCES = ["integrals.hip", "gemm.hip", "linalg.hip", "factors.hip", "davidson.hip", "risp_abi.hip"]
+SOURCES = ["integrals.hip", "gemm.hip", "gemm_bf16.hip", "linalg.hip", "factors.hip", "subspace.hip", "davidson.hip",
+           "serve.hip", "risp_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}",

@@ -1,12 +1,18 @@
 // Block Davidson on the device.
 #pragma once
 
+#include <chrono>
 #include <functional>
 #include <vector>
 
 #include "factors.hpp"
 
 namespace risp {
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double sec() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
 
 // sigma_fn(m, X_dev, S_dev): S = A X for m rows stored in the trial-vector type (FP64 for FP64
 // factors, FP32 otherwise). Must be stream-ordered on the context stream.
@@ -34,6 +40,54 @@ struct DavResult {
   bool stalled = false;
   double t_sigma = 0.0, t_subspace = 0.0, sigma_flops = 0.0;
   std::vector<double> resid_hist;  // max residual over the nstates per iteration
+};
+
+// One Davidson solve as a resumable state machine: next() names the sigma block it needs (rows of
+// V to multiply into the same rows of W), complete() consumes it and advances. Everything except
+// the sigma products runs inside complete() on the run's stream.
+class DavidsonRun {
+ public:
+  struct Request {
+    int r0 = 0, n = 0;
+    void* X = nullptr;  // device rows of V
+    void* S = nullptr;  // device rows of W to fill
+  };
+  DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s);
+  bool next(Request& rq) const;  // false when finished
+  void complete();
+  bool done() const { return state_ == State::Done; }
+  DavResult& result() { return res_; }
+
+ private:
+  enum class State { Init, Append, Restart, Done };
+  void* vrow(DevBuf& b, int r);
+  void update_H(int nall, int n0, int nn);
+  void row_norms(const double* R, int k, double* out_dev);
+  void combine_rows(const double* Cm, int ldcm, int nsub, int k, const void* Vsrc, double* out, double alpha,
+                    double beta);
+  int orth_block(int nt);
+  void project_out(int nsub, int nt);
+  void store_T(int r0, int n);
+  void iterate(Timer& tsub);
+  void append_corrections(int nt, Timer& tsub);
+  void finish(Timer& tsub);
+
+  risp_factors* f_;
+  DavOptions o_;
+  hipStream_t s_;
+  int64_t ov_ = 0;
+  bool fp64_ = false;
+  DType tvec_ = DType::F32;
+  size_t vsz_ = 4;
+  int nstates_ = 0, block_ = 0, max_space_ = 0, cap_ = 0, ld_ = 0, max_iter_ = 0, nblk_ = 1;
+  int nsub_ = 0, nt_saved_ = 0, best_it_ = 0;
+  double best_r_ = 1e300;
+  State state_ = State::Init;
+  Request rq_;
+  DavResult res_;
+  std::vector<double> hnorm_, htheta_;
+  DevBuf V_, W_, H_, Hw_, Zs_, eigws_, theta_, AX_, T_, T2_, Tsave_, Cmix_, G_, Cf_, partial_, norms_, kept_,
+      src_, Hn_, split_;
 };
 
 void davidson(risp_factors* f, const DavOptions& o, const SigmaFn& sigma_fn, DavResult& res);

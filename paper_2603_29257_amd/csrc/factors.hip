@@ -36,10 +36,10 @@ void risp_ctx::clear_phases() {
 
 namespace risp {
 
-PhaseScope::PhaseScope(risp_ctx* c, int ph, double flops, double bytes) : c_(c), ph_(ph) {
+PhaseScope::PhaseScope(risp_ctx* c, hipStream_t s, int ph, double flops, double bytes) : c_(c), s_(s), ph_(ph) {
   if (!c_->profiling) return;
   RISP_HIP(hipEventCreate(&a_));
-  RISP_HIP(hipEventRecord(a_, c_->stream));
+  RISP_HIP(hipEventRecord(a_, s_));
   PhaseLog& p = c_->phase[ph_];
   p.launches += 1;
   p.flops += flops;
@@ -50,7 +50,7 @@ PhaseScope::~PhaseScope() noexcept(false) {
   if (!a_) return;
   hipEvent_t b = nullptr;
   RISP_HIP(hipEventCreate(&b));
-  RISP_HIP(hipEventRecord(b, c_->stream));
+  RISP_HIP(hipEventRecord(b, s_));
   c_->phase[ph_].pending.emplace_back(a_, b);
 }
 
@@ -136,10 +136,9 @@ __global__ void k_mul_scales(const float* a, const float* b, float* c, int n) {
 
 // T~[P][p][q] = C_l^T (mu nu|P) C_r over auxiliary shells, chunked; V = (mu nu|op|P) FP64.
 // CLT [nl][nao], CRT [nr][nao] (transposed MO coefficient blocks). Out: FP64 [nfunc][nl][nr].
-static void transformed_3c(risp_ctx* ctx, const DevShells& ao, const PairList& pairs,
+static void transformed_3c(risp_ctx* ctx, hipStream_t s, const DevShells& ao, const PairList& pairs,
                            const DevShells& aux, const Operator& op, const double* CLT, int nl,
                            const double* CRT, int nr, double* out) {
-  hipStream_t s = ctx->stream;
   const int nao = ao.nfunc;
   // auxiliary shell chunks of at most ~2 GB of FP64 integrals
   const int64_t per_func = (int64_t)nao * nao * 8;
@@ -201,8 +200,8 @@ static void metric_apply(const double* Linv, int n, const double* T, int64_t col
   }
 }
 
-static void metric_inverse_cholesky(risp_ctx* ctx, const DevShells& aux, const Operator& op, DevBuf& Linv) {
-  hipStream_t s = ctx->stream;
+static void metric_inverse_cholesky(risp_ctx* ctx, hipStream_t s, const DevShells& aux, const Operator& op,
+                                    DevBuf& Linv) {
   const int n = aux.nfunc;
   DevBuf V((size_t)n * n * 8);
   int2c(aux, op, ctx->boys.as<double>(), V.as<double>(), s);
@@ -212,7 +211,8 @@ static void metric_inverse_cholesky(risp_ctx* ctx, const DevShells& aux, const O
   RISP_HIP(hipStreamSynchronize(s));
 }
 
-void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, risp_factors* f) {
+void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, risp_factors* f,
+                   hipStream_t stream) {
   validate_system(sys);
   RISP_CHECK(prm != nullptr, RISP_E_ARG, "params is NULL");
   RISP_CHECK(prm->precision >= RISP_FP64 && prm->precision <= RISP_BF16, RISP_E_ARG, "bad precision");
@@ -222,9 +222,10 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   RISP_CHECK(prm->theta > 0.0 && prm->schwarz_tau >= 0.0 && prm->omega >= 0.0, RISP_E_ARG,
              "theta must be positive, tau and omega non-negative");
   RISP_CHECK(prm->beta == 0.0 || prm->omega > 0.0, RISP_E_ARG, "beta != 0 needs omega > 0");
-  hipStream_t s = ctx->stream;
+  hipStream_t s = stream ? stream : ctx->stream;
   const int nao = sys->nao, nmo = sys->nmo, nocc = sys->nocc, nvir = nmo - nocc;
   f->ctx = ctx;
+  f->stream = s;
   f->nao = nao;
   f->nmo = nmo;
   f->nocc = nocc;
@@ -271,10 +272,10 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   {
     Operator coul;  // 1/r
     DevBuf Linv;
-    metric_inverse_cholesky(ctx, aj, coul, Linv);
+    metric_inverse_cholesky(ctx, s, aj, coul, Linv);
     const int64_t ov = (int64_t)nocc * nvir;
     DevBuf Tt((size_t)aj.nfunc * ov * 8);
-    transformed_3c(ctx, ao, pairs, aj, coul, CoT.as<double>(), nocc, CvT.as<double>(), nvir, Tt.as<double>());
+    transformed_3c(ctx, s, ao, pairs, aj, coul, CoT.as<double>(), nocc, CvT.as<double>(), nvir, Tt.as<double>());
     DevBuf B((size_t)aj.nfunc * ov * 8);
     metric_apply(Linv.as<double>(), aj.nfunc, Tt.as<double>(), ov, B.as<double>(), s);
     Tt.release();
@@ -322,11 +323,11 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     DevBuf Bij((size_t)nK * nok * nok * 8), Bab((size_t)nK * nvk * nvk * 8);
     for (size_t blk = 0; blk < blocks.size(); ++blk) {
       DevBuf Linv;
-      metric_inverse_cholesky(ctx, ak, blocks[blk], Linv);
+      metric_inverse_cholesky(ctx, s, ak, blocks[blk], Linv);
       DevBuf Tij((size_t)nks * nok * nok * 8), Tab((size_t)nks * nvk * nvk * 8);
-      transformed_3c(ctx, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
+      transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
                      Tij.as<double>());
-      transformed_3c(ctx, ao, pairs, ak, blocks[blk], CvKT.as<double>(), nvk, CvKT.as<double>(), nvk,
+      transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CvKT.as<double>(), nvk, CvKT.as<double>(), nvk,
                      Tab.as<double>());
       metric_apply(Linv.as<double>(), nks, Tij.as<double>(), (int64_t)nok * nok,
                    Bij.as<double>() + blk * (size_t)nks * nok * nok, s);
@@ -404,6 +405,12 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   f->ws_csz = cs;
 }
 
+void sigma_prepare(risp_factors* f, int m, bool use_f32) {
+  const bool bf = f->precision == RISP_BF16 && !use_f32;
+  const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
+  ensure_workspace(f, m, tc, f->stream);
+}
+
 static void need(const DevBuf& b, size_t bytes, const char* what) {
   RISP_CHECK(b.bytes() >= bytes, RISP_E_STATE, std::string("sigma workspace too small: ") + what);
 }
@@ -429,14 +436,14 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   // Coulomb pass 1: Y[P][m] = s_P^2 sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
   const void* Xc = X;
   if (bf) {
-    PhaseScope po(f->ctx, RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
+    PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
     convert(X, DType::F32, f->ws_xbf.get(), DType::BF16, m * ov, s);
     Xc = f->ws_xbf.get();
   }
   const float* rs = bf ? f->scale_ia2.as<float>() : nullptr;  // s_P^2 folded into Y (exact)
   const size_t esz = dtype_size(tc);
   {
-    PhaseScope ps(f->ctx, RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * m,
+    PhaseScope ps(f->ctx, s, RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * m,
                   (double)esz * ((double)nJ * ov + (double)m * ov) + 4.0 * nJ * m);
     Gemm g;
     g.M = nJ;
@@ -460,11 +467,11 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   {
     const void* Yc = f->ws_y.get();
     if (bf) {
-      PhaseScope po(f->ctx, RISP_PHASE_OTHER, 0.0, 6.0 * nJ * m);
+      PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0, 6.0 * nJ * m);
       convert(f->ws_y.get(), DType::F32, f->ws_ybf.get(), DType::BF16, (int64_t)nJ * m, s);
       Yc = f->ws_ybf.get();
     }
-    PhaseScope ps(f->ctx, RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * m,
+    PhaseScope ps(f->ctx, s, RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * m,
                   (double)esz * ((double)nJ * ov + (double)nJ * m) + (double)dtype_size(tv) * m * ov);
     Gemm g;
     g.M = m;
@@ -488,7 +495,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   const bool exch = nK > 0 && nok > 0 && nvk > 0;
   if (exch) {
     {
-      PhaseScope po(f->ctx, RISP_PHASE_OTHER, 0.0,
+      PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0,
                     (double)m * nok * nvk * (dtype_size(tv) + dtype_size(tc)));
       gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
                     f->ws_xw.get(), tc, s);
@@ -502,7 +509,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
     for (int P0 = 0; P0 < nK; P0 += pc) {
       const int np = std::min(pc, nK - P0);
       // GEMM1: Mt[m][a][(p, j)] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]
-      std::optional<PhaseScope> ps1(std::in_place, f->ctx, RISP_PHASE_EXCHANGE_M,
+      std::optional<PhaseScope> ps1(std::in_place, f->ctx, s, RISP_PHASE_EXCHANGE_M,
                                     2.0 * m * np * (double)nvk * nvk * nok,
                                     (double)csz * ((double)np * nvk * nvk + (double)m * nok * nvk +
                                                    (double)m * np * nvk * nok));
@@ -530,7 +537,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       gemm(g1, nullptr, s);
       ps1.reset();
       // GEMM2: K[m][i][a] += sum_(p, j) T_ij[i][(P0 + p) j] Mt[m][a][(p, j)]
-      PhaseScope ps2(f->ctx, RISP_PHASE_EXCHANGE_K, 2.0 * m * (double)nok * np * nok * nvk,
+      PhaseScope ps2(f->ctx, s, RISP_PHASE_EXCHANGE_K, 2.0 * m * (double)nok * np * nok * nvk,
                      (double)csz * ((double)nok * np * nok + (double)m * np * nvk * nok) +
                          (double)dtype_size(tacc) * m * nok * nvk * (P0 > 0 ? 2.0 : 1.0));
       Gemm g2;
@@ -552,7 +559,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       gemm(g2, nullptr, s);
     }
   }
-  PhaseScope po(f->ctx, RISP_PHASE_OTHER, (double)m * ov * 3.0,
+  PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, (double)m * ov * 3.0,
                 (double)m * ov * dtype_size(tv) * 3.0 + (double)m * nok * nvk * dtype_size(tacc));
   combine_sigma(sig, X, tv, f->de64.as<double>(), f->de32.as<float>(), m, f->nocc, f->nvir,
                 exch ? f->ws_k.get() : nullptr, tacc, f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk, s);

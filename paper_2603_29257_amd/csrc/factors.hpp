@@ -10,6 +10,7 @@
 struct risp_factors;
 
 namespace risp {
+struct Server;
 // Event-timed launches of one sigma phase.
 struct PhaseLog {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -26,6 +27,12 @@ struct risp_ctx {
   std::set<risp_factors*> factors;  // live factor objects (detached when the context goes away)
   bool profiling = false;
   risp::PhaseLog phase[RISP_NPHASE];
+  // serving
+  risp::Server* server = nullptr;
+  hipStream_t serve_stream = nullptr;
+  int64_t serve_budget = 0;
+  int serve_max_active = 0;
+  int serve_graphs = 1;
   void resolve_phases();  // fold pending events into ms (synchronises)
   void clear_phases();
 };
@@ -34,11 +41,12 @@ namespace risp {
 // Records HIP events around the launches issued during its lifetime when profiling is on.
 class PhaseScope {
  public:
-  PhaseScope(risp_ctx* c, int ph, double flops, double bytes);
+  PhaseScope(risp_ctx* c, hipStream_t s, int ph, double flops, double bytes);
   ~PhaseScope() noexcept(false);
 
  private:
   risp_ctx* c_;
+  hipStream_t s_;
   int ph_;
   hipEvent_t a_ = nullptr;
 };
@@ -46,6 +54,7 @@ class PhaseScope {
 
 struct risp_factors {
   risp_ctx* ctx = nullptr;
+  hipStream_t stream = nullptr;  // stream of this object's work (the context stream, or a job stream)
   int nao = 0, nmo = 0, nocc = 0, nvir = 0;
   int naux_j = 0, naux_k = 0, nok = 0, nvk = 0, npair = 0;
   int precision = RISP_FP32;
@@ -69,10 +78,15 @@ namespace risp {
 // accumulation; `use_f32` selects the FP32 copies of BF16 factors.
 void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s);
 
+// size the sigma workspaces for m vectors ahead of a graph capture (their allocation synchronises)
+void sigma_prepare(risp_factors* f, int m, bool use_f32);
+
 // algorithmic flops of one sigma block of m vectors
 double sigma_flops(const risp_factors* f, int m);
 
-void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, risp_factors* f);
+// Builds on `stream` (the context stream when null); f->stream is set to it.
+void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, risp_factors* f,
+                   hipStream_t stream = nullptr);
 
 void validate_system(const risp_system* sys);
 void select_aux(const risp_system* sys, const risp_params* prm, std::vector<risp_shell>& J,

@@ -272,6 +272,14 @@ __global__ void k_gemm_reduce(Gemm g, const Acc* __restrict__ work, int nbatch) 
   }
 }
 
+template <typename Acc, typename TO>
+static void reduce_split(const Gemm& g, void* work, hipStream_t s) {
+  const int64_t total = (int64_t)g.nb1 * g.nb2 * g.M * g.N;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
+  k_gemm_reduce<Acc, TO><<<grid, 256, 0, s>>>(g, static_cast<const Acc*>(work), g.nb1 * g.nb2);
+  RISP_LAUNCHED();
+}
+
 template <typename TI> static int tile_m() { return MF<TI>::BM; }
 template <typename TI> static int tile_n() { return MF<TI>::BN; }
 
@@ -303,13 +311,7 @@ static void launch(const Gemm& g, void* work, hipStream_t s) {
     k_gemm<TMA, TMB, TI, TO><<<dim3(tm * tn, zc), 256, 0, s>>>(g, (int)z0, work);
     RISP_LAUNCHED();
   }
-  if (g.ksplit > 1) {
-    using Acc = typename MF<TI>::Acc;
-    const int64_t total = (int64_t)g.nb1 * g.nb2 * g.M * g.N;
-    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
-    k_gemm_reduce<Acc, TO><<<grid, 256, 0, s>>>(g, static_cast<const Acc*>(work), g.nb1 * g.nb2);
-    RISP_LAUNCHED();
-  }
+  if (g.ksplit > 1) reduce_split<typename MF<TI>::Acc, TO>(g, work, s);
 }
 
 void gemm(const Gemm& g, void* work, hipStream_t s) {
@@ -338,6 +340,14 @@ void gemm(const Gemm& g, void* work, hipStream_t s) {
     }
   } else {
     RISP_CHECK(ma == g.tin && mb == g.tin, RISP_E_ARG, "gemm: FP32/BF16 products read their own type");
+    if (gemm_bf16_nt_eligible(g)) {
+      gemm_bf16_nt(g, work, s);
+      if (g.ksplit > 1) {
+        if (g.tout == DType::F32) reduce_split<float, float>(g, work, s);
+        else reduce_split<float, bfs>(g, work, s);
+      }
+      return;
+    }
     if (g.tin == DType::F32) {
       if (g.tout == DType::F32) launch<float, float, float, float>(g, work, s);
       else if (g.tout == DType::F64) launch<float, float, float, double>(g, work, s);

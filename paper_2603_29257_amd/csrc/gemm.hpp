@@ -46,6 +46,10 @@ struct Gemm {
 size_t gemm_workspace_bytes(const Gemm& g);
 void gemm(const Gemm& g, void* work, hipStream_t s);
 
+// Tuned BF16 kernel for contraction-contiguous operands (used by gemm() when eligible).
+bool gemm_bf16_nt_eligible(const Gemm& g);
+void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s);
+
 // Choose a split-K factor so that the grid covers the chip (about 2048 blocks) for skinny
 // products; returns 1 when tiles alone suffice.
 int gemm_auto_split(const Gemm& g);

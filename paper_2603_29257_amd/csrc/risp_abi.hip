@@ -8,6 +8,7 @@
 #include "factors.hpp"
 #include "integrals.hpp"
 #include "linalg.hpp"
+#include "serve.hpp"
 
 namespace risp {
 static thread_local std::string g_last_error;
@@ -95,6 +96,7 @@ risp_status risp_ctx_destroy(risp_ctx* ctx) {
   return guarded([&]() -> risp_status {
     if (!ctx) return RISP_OK;
     (void)hipSetDevice(ctx->device);
+    stop_server(ctx);  // finishes resident jobs, drops queued ones
     (void)hipStreamSynchronize(ctx->stream);
     try {
       ctx->clear_phases();
@@ -325,7 +327,7 @@ risp_status risp_sigma(risp_ctx* ctx, const risp_factors* fc, int32_t m, const v
     const int want = fc->precision == RISP_FP64 ? RISP_FP64 : RISP_FP32;
     RISP_CHECK(dtype == want, RISP_E_ARG,
                want == RISP_FP64 ? "FP64 factors take FP64 vectors" : "FP32/BF16 factors take FP32 vectors");
-    sigma(const_cast<risp_factors*>(fc), m, X_dev, sigma_dev, false, ctx->stream);
+    sigma(const_cast<risp_factors*>(fc), m, X_dev, sigma_dev, false, fc->stream);
     return RISP_OK;
   });
 }
@@ -338,7 +340,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
     RISP_CHECK(fc->ctx == ctx, RISP_E_STATE, "factors belong to another context");
     risp_factors* f = const_cast<risp_factors*>(fc);
     const int64_t ov = (int64_t)f->nocc * f->nvir;
-    hipStream_t s = ctx->stream;
+    hipStream_t s = f->stream;
     DavOptions o;
     o.nstates = opts->nstates;
     o.block = opts->block;
@@ -418,6 +420,54 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       set_last_error("Davidson did not converge within max_iter");
       return (risp_status)RISP_E_NOTCONV;
     }
+    return RISP_OK;
+  });
+}
+
+risp_status risp_serve_config(risp_ctx* ctx, const risp_serve_opts* opts) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(opts != nullptr, RISP_E_ARG, "opts is NULL");
+    RISP_CHECK(ctx->server == nullptr, RISP_E_STATE, "serving already started");
+    RISP_CHECK(opts->hbm_budget_bytes >= 0 && opts->max_active >= 0, RISP_E_ARG, "negative serving limits");
+    ctx->serve_budget = opts->hbm_budget_bytes;
+    ctx->serve_max_active = opts->max_active;
+    ctx->serve_graphs = opts->use_graphs;
+    return RISP_OK;
+  });
+}
+
+risp_status risp_job_footprint(const risp_system* sys, const risp_params* prm, const risp_dav_opts* opts,
+                               int64_t* bytes) {
+  return guarded([&]() -> risp_status {
+    validate_system(sys);
+    RISP_CHECK(prm && bytes, RISP_E_ARG, "NULL argument");
+    *bytes = job_footprint(sys, prm, opts);
+    return RISP_OK;
+  });
+}
+
+risp_status risp_submit(risp_ctx* ctx, const risp_system* sys, const risp_params* prm, const risp_dav_opts* opts,
+                        uint64_t* job_id) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(job_id != nullptr, RISP_E_ARG, "job_id is NULL");
+    *job_id = submit_job(ctx, sys, prm, opts);
+    return RISP_OK;
+  });
+}
+
+risp_status risp_poll(risp_ctx* ctx, uint64_t job_id, risp_result* out) {
+  return guarded([&]() -> risp_status {
+    RISP_CHECK(ctx && out, RISP_E_ARG, "NULL argument");
+    return poll_job(ctx, job_id, out);
+  });
+}
+
+risp_status risp_serve_stats_get(risp_ctx* ctx, risp_serve_stats* out) {
+  return guarded([&]() -> risp_status {
+    RISP_CHECK(ctx && out, RISP_E_ARG, "NULL argument");
+    serve_stats(ctx, out);
     return RISP_OK;
   });
 }

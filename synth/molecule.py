@@ -142,21 +142,29 @@ class _Skeleton:
         n_old = len(self.xyz)
         if np.any(np.linalg.norm(new_xyz, axis=1) > self.R):
             return True
-        nb = [set(s) for s in self.nbr] + [set() for _ in range(len(new_xyz))]
+        extra: dict[int, set] = {}  # tentative bonds, without copying the whole neighbour list
         for a, b in new_bonds:
-            nb[a].add(b)
-            nb[b].add(a)
+            extra.setdefault(a, set()).add(b)
+            extra.setdefault(b, set()).add(a)
+
+        def nb(t):
+            base = self.nbr[t] if t < n_old else set()
+            return base | extra.get(t, set())
+
         allxyz = np.vstack([self.xyz, new_xyz]) if n_old else new_xyz
         for k in range(len(new_xyz)):
             idx = n_old + k
-            excl = {idx} | nb[idx]  # graph distance <= 2 is bonded geometry, not a clash
-            for q in list(nb[idx]):
-                excl |= nb[q]
-            others = np.array([t for t in range(n_old + k) if t not in excl], dtype=np.int64)
-            if len(others):
-                d = np.linalg.norm(allxyz[others] - allxyz[idx], axis=1)
-                if np.any(d < 2.5):
-                    return True
+            if idx == 0:
+                continue
+            d = np.linalg.norm(allxyz[:idx] - allxyz[idx], axis=1)
+            close = np.nonzero(d < 2.5)[0]
+            if len(close) == 0:
+                continue
+            excl = {idx} | nb(idx)  # graph distance <= 2 is bonded geometry, not a clash
+            for q in list(nb(idx)):
+                excl |= nb(q)
+            if any(int(t) not in excl for t in close):
+                return True
         return False
 
     def _commit(self, new_xyz, new_bonds):

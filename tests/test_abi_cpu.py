@@ -67,3 +67,24 @@ def test_host_side_argument_errors_without_gpu():
                                   ctypes.byref(nk))
     assert rc == abi.RISP_E_ARG
     assert np.all([J[k].atom < 12 for k in range(24)])
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librisp.so not built")
+def test_job_footprint_host_model():
+    """The admission footprint is host logic: it grows with size, precision and subspace."""
+    from paper_2603_29257_amd import abi
+    import synth
+    small = abi.System(synth.make_chain_ring(40, 40))
+    big = abi.System(synth.make_config0())
+    f_small = abi.job_footprint(small, abi.Params(precision=abi.FP32), nstates=5)
+    f_big = abi.job_footprint(big, abi.Params(precision=abi.FP32), nstates=5)
+    assert 0 < f_small
+    f64 = abi.job_footprint(small, abi.Params(precision=abi.FP64), nstates=5)
+    assert f64 > f_small
+    more = abi.job_footprint(small, abi.Params(precision=abi.FP32), nstates=5, max_space=200)
+    assert more >= f_small
+    assert f_big != f_small
+    with pytest.raises(abi.RispError):
+        bad = synth.make_chain_ring(40, 40)
+        bad.nocc = 0
+        abi.job_footprint(abi.System(bad), abi.Params(), nstates=5)
