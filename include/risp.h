@@ -129,13 +129,16 @@ typedef struct {
   int32_t npair;          /* shell pairs kept by screening */
   int32_t precision;
   int64_t bytes;          /* device bytes held by the factor object */
-  const void *t_ia;       /* dev [naux_j][nocc][nvir] in `precision` (BF16: stored / scale) */
-  const void *t_ij;       /* dev [nocc_k][naux_k][nocc_k] */
-  const void *t_ab;       /* dev [naux_k][nvir_k][nvir_k] */
+  const void *t_ia;       /* dev [naux_j][ld_ia], row = (i, a) pairs nocc*nvir then zero padding,
+                             in `precision` (BF16: stored / scale) */
+  const void *t_ij;       /* dev [nocc_k][naux_k][ld_ij], last index j < nocc_k, rest zero */
+  const void *t_ab;       /* dev [naux_k][nvir_k][ld_ab], last index b < nvir_k, rest zero */
   const float *scale_ia;  /* dev [naux_j] power-of-two scales (BF16), else NULL */
   const float *scale_k;   /* dev [naux_k] product of the T_ij and T_ab scales (BF16), else NULL */
   const int32_t *occ_k;   /* dev [nocc_k] window occupied indices, ascending */
   const int32_t *vir_k;   /* dev [nvir_k] window virtual indices (0-based in the virtual space) */
+  int64_t ld_ia;          /* row stride of t_ia: nocc*nvir rounded up to a multiple of 8 */
+  int32_t ld_ij, ld_ab;   /* row strides of t_ij and t_ab: nocc_k, nvir_k rounded up likewise */
 } risp_factors_desc;
 
 /* Per-phase timing of sigma products (HIP events on the context stream around each launch). */

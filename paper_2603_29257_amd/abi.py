@@ -81,7 +81,8 @@ class FactorsDescC(C.Structure):
                 ("naux_j", C.c_int32), ("naux_k", C.c_int32), ("nocc_k", C.c_int32), ("nvir_k", C.c_int32),
                 ("npair", C.c_int32), ("precision", C.c_int32), ("bytes", C.c_int64),
                 ("t_ia", C.c_void_p), ("t_ij", C.c_void_p), ("t_ab", C.c_void_p), ("scale_ia", C.c_void_p),
-                ("scale_k", C.c_void_p), ("occ_k", C.c_void_p), ("vir_k", C.c_void_p)]
+                ("scale_k", C.c_void_p), ("occ_k", C.c_void_p), ("vir_k", C.c_void_p),
+                ("ld_ia", C.c_int64), ("ld_ij", C.c_int32), ("ld_ab", C.c_int32)]
 
 
 class ServeOptsC(C.Structure):
@@ -242,22 +243,33 @@ class Factors:
         except Exception:
             pass
 
-    def tensor(self, which):
-        """Copy of a stored factor or index set as a torch tensor on the device."""
+    def tensor(self, which, padded=False):
+        """Copy of a stored factor or index set as a torch tensor on the device.
+
+        Factors are stored with rows padded to a multiple of 8 elements; the copy is returned with
+        the padding removed unless `padded` is set (then the last axis has the stored length)."""
         import torch
         d = self.desc
         dt = {FP64: torch.float64, FP32: torch.float32, BF16: torch.bfloat16}[d.precision]
-        shapes = {"t_ia": ((d.naux_j, d.nocc, d.nvir), dt), "t_ij": ((d.nocc_k, d.naux_k, d.nocc_k), dt),
-                  "t_ab": ((d.naux_k, d.nvir_k, d.nvir_k), dt), "scale_ia": ((d.naux_j,), torch.float32),
+        shapes = {"t_ia": ((d.naux_j, d.ld_ia), dt), "t_ij": ((d.nocc_k, d.naux_k, d.ld_ij), dt),
+                  "t_ab": ((d.naux_k, d.nvir_k, d.ld_ab), dt), "scale_ia": ((d.naux_j,), torch.float32),
                   "scale_k": ((d.naux_k,), torch.float32), "occ_k": ((d.nocc_k,), torch.int32),
                   "vir_k": ((d.nvir_k,), torch.int32)}
         shape, dtype = shapes[which]
         ptr = getattr(d, which)
-        out = torch.empty(shape, dtype=dtype, device=self.ctx.device)
+        out = torch.zeros(shape, dtype=dtype, device=self.ctx.device)
         if ptr and out.numel():
             nbytes = out.numel() * out.element_size()
             self.ctx.synchronize()
             _memcpy_d2d(out.data_ptr(), ptr, nbytes)
+        if padded:
+            return out
+        if which == "t_ia":
+            return out[:, :d.nocc * d.nvir].reshape(d.naux_j, d.nocc, d.nvir)
+        if which == "t_ij":
+            return out[:, :, :d.nocc_k]
+        if which == "t_ab":
+            return out[:, :, :d.nvir_k]
         return out
 
 

@@ -98,34 +98,40 @@ static Gemm g64(int M, int N, int K) {
   return g;
 }
 
-// Stored factor of `rows` auxiliary slices of `cols` values, from the FP64 matrix B [rows][cols].
+// Stored factor: `rows` rows of `cols` values padded to `ldd` (a multiple of 8, zero padding), in the
+// storage precision; BF16 rows are divided by the power-of-two scale of their auxiliary slice
+// (scale index (row / div) % mod). An FP32 copy with the same layout is kept next to BF16 factors.
 struct Stored {
-  DevBuf main, f32, scale;
+  DevBuf main, f32;
 };
-static void store_factor(const double* B, int rows, int64_t cols, int precision, bool keep_f32,
-                         bool bf16_scale, Stored& out, hipStream_t s) {
-  const int64_t n = (int64_t)rows * cols;
+static void store_factor(const double* B, int64_t rows, int64_t cols, int64_t ldd, int precision, bool keep_f32,
+                         const float* scale, int64_t div, int64_t mod, Stored& out, hipStream_t s) {
+  const int64_t n = std::max<int64_t>(rows * ldd, 1);
   if (precision == RISP_FP64) {
-    out.main.alloc(std::max<int64_t>(n, 1) * 8);
-    convert(B, DType::F64, out.main.get(), DType::F64, n, s);
+    out.main.alloc(n * 8);
+    store_rows_padded(B, DType::F64, cols, rows, cols, out.main.get(), DType::F64, ldd, nullptr, 1, 1, s);
   } else if (precision == RISP_FP32) {
-    out.main.alloc(std::max<int64_t>(n, 1) * 4);
-    convert(B, DType::F64, out.main.get(), DType::F32, n, s);
+    out.main.alloc(n * 4);
+    store_rows_padded(B, DType::F64, cols, rows, cols, out.main.get(), DType::F32, ldd, nullptr, 1, 1, s);
   } else {
-    out.main.alloc(std::max<int64_t>(n, 1) * 2);
-    out.scale.alloc(std::max(rows, 1) * sizeof(float));
-    if (bf16_scale) {
-      scale_rows_bf16(B, rows, cols, out.scale.as<float>(), out.main.get(), s);
-    } else {
-      std::vector<float> ones(std::max(rows, 1), 1.0f);
-      RISP_HIP(hipMemcpyAsync(out.scale.get(), ones.data(), ones.size() * 4, hipMemcpyHostToDevice, s));
-      convert(B, DType::F64, out.main.get(), DType::BF16, n, s);
-      RISP_HIP(hipStreamSynchronize(s));
-    }
+    out.main.alloc(n * 2);
+    store_rows_padded(B, DType::F64, cols, rows, cols, out.main.get(), DType::BF16, ldd, scale, div, mod, s);
     if (keep_f32) {
-      out.f32.alloc(std::max<int64_t>(n, 1) * 4);
-      convert(B, DType::F64, out.f32.get(), DType::F32, n, s);
+      out.f32.alloc(n * 4);
+      store_rows_padded(B, DType::F64, cols, rows, cols, out.f32.get(), DType::F32, ldd, nullptr, 1, 1, s);
     }
+  }
+}
+
+// power-of-two scales of `slices` contiguous FP64 slices of `len` values (ones when disabled)
+static void slice_scales(const double* B, int slices, int64_t len, bool enabled, DevBuf& out, hipStream_t s) {
+  out.alloc(std::max(slices, 1) * sizeof(float));
+  if (enabled) {
+    row_pow2_scales(B, slices, len, out.as<float>(), s);
+  } else {
+    std::vector<float> ones(std::max(slices, 1), 1.0f);
+    RISP_HIP(hipMemcpyAsync(out.get(), ones.data(), ones.size() * 4, hipMemcpyHostToDevice, s));
+    RISP_HIP(hipStreamSynchronize(s));
   }
 }
 
@@ -279,12 +285,14 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     DevBuf B((size_t)aj.nfunc * ov * 8);
     metric_apply(Linv.as<double>(), aj.nfunc, Tt.as<double>(), ov, B.as<double>(), s);
     Tt.release();
+    f->ld_ia = pad8(ov);
+    if (prm->precision == RISP_BF16) slice_scales(B.as<double>(), aj.nfunc, ov, prm->bf16_scale != 0, f->scale_ia, s);
     Stored st;
-    store_factor(B.as<double>(), aj.nfunc, ov, prm->precision, f->has_f32, prm->bf16_scale != 0, st, s);
+    store_factor(B.as<double>(), aj.nfunc, ov, f->ld_ia, prm->precision, f->has_f32, f->scale_ia.as<float>(), 1,
+                 aj.nfunc, st, s);
     RISP_HIP(hipStreamSynchronize(s));
     f->t_ia = std::move(st.main);
     f->t_ia32 = std::move(st.f32);
-    f->scale_ia = std::move(st.scale);
     if (prm->precision == RISP_BF16) {
       f->scale_ia2.alloc(aj.nfunc * sizeof(float));
       k_mul_scales<<<ceil_div(aj.nfunc, 256), 256, 0, s>>>(f->scale_ia.as<float>(), f->scale_ia.as<float>(),
@@ -335,23 +343,36 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
                    Bab.as<double>() + blk * (size_t)nks * nvk * nvk, s);
       RISP_HIP(hipStreamSynchronize(s));
     }
-    // T_ij stored [i][P][j] for the second exchange product; T_ab [P][a][b]
-    Stored sij, sab;
-    store_factor(Bij.as<double>(), nK, (int64_t)nok * nok, prm->precision, f->has_f32, prm->bf16_scale != 0, sij, s);
-    store_factor(Bab.as<double>(), nK, (int64_t)nvk * nvk, prm->precision, f->has_f32, prm->bf16_scale != 0, sab, s);
-    const size_t esz = prm->precision == RISP_FP64 ? 8 : (prm->precision == RISP_FP32 ? 4 : 2);
-    f->t_ij.alloc(std::max<size_t>((size_t)nK * nok * nok * esz, 8));
-    permute_pij_ipj(sij.main.get(), nK, nok, nok, esz, f->t_ij.get(), s);
-    f->t_ab = std::move(sab.main);
-    if (f->has_f32) {
-      f->t_ij32.alloc(std::max<size_t>((size_t)nK * nok * nok * 4, 8));
-      permute_pij_ipj(sij.f32.get(), nK, nok, nok, 4, f->t_ij32.get(), s);
-      f->t_ab32 = std::move(sab.f32);
+    // T_ij stored [i][P][j] (j padded) for the second exchange product; T_ab [P][a][b] (b padded)
+    f->nokp = (int)pad8(nok);
+    f->nvkp = (int)pad8(nvk);
+    DevBuf sij, sab;
+    const bool bf = prm->precision == RISP_BF16;
+    if (bf) {
+      slice_scales(Bij.as<double>(), nK, (int64_t)nok * nok, prm->bf16_scale != 0, sij, s);
+      slice_scales(Bab.as<double>(), nK, (int64_t)nvk * nvk, prm->bf16_scale != 0, sab, s);
     }
-    if (prm->precision == RISP_BF16) {
+    {
+      DevBuf Bp((size_t)nK * nok * nok * 8);  // FP64 [i][P][j]
+      permute_pij_ipj(Bij.as<double>(), nK, nok, nok, 8, Bp.get(), s);
+      Stored st;
+      store_factor(Bp.as<double>(), (int64_t)nok * nK, nok, f->nokp, prm->precision, f->has_f32, sij.as<float>(), 1,
+                   nK, st, s);
+      RISP_HIP(hipStreamSynchronize(s));
+      f->t_ij = std::move(st.main);
+      f->t_ij32 = std::move(st.f32);
+    }
+    {
+      Stored st;
+      store_factor(Bab.as<double>(), (int64_t)nK * nvk, nvk, f->nvkp, prm->precision, f->has_f32, sab.as<float>(),
+                   nvk, nK, st, s);
+      RISP_HIP(hipStreamSynchronize(s));
+      f->t_ab = std::move(st.main);
+      f->t_ab32 = std::move(st.f32);
+    }
+    if (bf) {
       f->scale_k.alloc(nK * sizeof(float));
-      k_mul_scales<<<ceil_div(nK, 256), 256, 0, s>>>(sij.scale.as<float>(), sab.scale.as<float>(),
-                                                    f->scale_k.as<float>(), nK);
+      k_mul_scales<<<ceil_div(nK, 256), 256, 0, s>>>(sij.as<float>(), sab.as<float>(), f->scale_k.as<float>(), nK);
       RISP_LAUNCHED();
     }
     RISP_HIP(hipStreamSynchronize(s));
@@ -387,17 +408,16 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   RISP_HIP(hipStreamSynchronize(s));  // workspaces may be in use by queued work
   m = std::max(m, f->ws_m);
   const int cs = std::max(csz, f->ws_csz);
-  const int64_t ov = (int64_t)f->nocc * f->nvir;
   const size_t acc = cs == 8 ? 8 : 4;
   f->ws_y.alloc((size_t)f->naux_j * m * acc);
   f->ws_ybf.alloc((size_t)f->naux_j * m * 2 + 16);
-  f->ws_xbf.alloc((size_t)m * ov * 2 + 16);
+  f->ws_xbf.alloc((size_t)m * f->ld_ia * 2 + 16);
   f->ws_split.alloc((size_t)kMaxSplit * f->naux_j * m * acc);
   if (f->naux_k > 0 && f->nok > 0 && f->nvk > 0) {
-    const int64_t per_p = (int64_t)m * f->nvk * f->nok;
+    const int64_t per_p = (int64_t)m * f->nvk * f->nokp;
     // P-chunk: intermediate M at most ~1 GiB and at least one slice
     const int64_t pc = std::max<int64_t>(1, std::min<int64_t>(f->naux_k, (1ll << 30) / (per_p * cs)));
-    f->ws_xw.alloc((size_t)m * f->nok * f->nvk * cs);
+    f->ws_xw.alloc((size_t)m * f->nokp * f->nvkp * cs);
     f->ws_mt.alloc((size_t)per_p * pc * cs);
     f->ws_k.alloc((size_t)m * f->nok * f->nvk * acc);
   }
@@ -424,9 +444,10 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   ensure_workspace(f, m, tc, s);
   const int64_t ov = (int64_t)f->nocc * f->nvir;
   const int nJ = f->naux_j;
+  const int64_t ldt = f->ld_ia;  // padded row stride of T_ia
   need(f->ws_y, (size_t)nJ * m * dtype_size(tacc), "Y");
   if (bf) {
-    need(f->ws_xbf, (size_t)m * ov * 2, "X (BF16)");
+    need(f->ws_xbf, (size_t)m * ldt * 2, "X (BF16)");
     need(f->ws_ybf, (size_t)nJ * m * 2, "Y (BF16)");
   }
   const void* Tia = (f->precision == RISP_BF16 && use_f32) ? f->t_ia32.get() : f->t_ia.get();
@@ -435,10 +456,12 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
 
   // Coulomb pass 1: Y[P][m] = s_P^2 sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
   const void* Xc = X;
-  if (bf) {
+  int64_t ldx = ov;
+  if (bf) {  // BF16 copy of X with the row stride of T_ia (zero padding)
     PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
-    convert(X, DType::F32, f->ws_xbf.get(), DType::BF16, m * ov, s);
+    store_rows_padded(X, DType::F32, ov, m, ov, f->ws_xbf.get(), DType::BF16, ldt, nullptr, 1, 1, s);
     Xc = f->ws_xbf.get();
+    ldx = ldt;
   }
   const float* rs = bf ? f->scale_ia2.as<float>() : nullptr;  // s_P^2 folded into Y (exact)
   const size_t esz = dtype_size(tc);
@@ -448,14 +471,14 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
     Gemm g;
     g.M = nJ;
     g.N = m;
-    g.K = (int)ov;
-    RISP_CHECK(ov < (1ll << 31), RISP_E_SHAPE, "nocc*nvir too large");
+    g.K = (int)(bf ? ldt : ov);  // BF16: the padding columns of T_ia and X are zero
+    RISP_CHECK(ldt < (1ll << 31), RISP_E_SHAPE, "nocc*nvir too large");
     g.tin = tc;
     g.tout = tacc;
     g.A = Tia;
-    g.lda = ov;
+    g.lda = ldt;
     g.B = Xc;
-    g.ldb = ov;
+    g.ldb = ldx;
     g.C = f->ws_y.get();
     g.ldc = m;
     g.row_scale = rs;
@@ -483,7 +506,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
     g.lda = m;
     g.a_kc = false;
     g.B = Tia;  // B[ia][P] = T[P][ia]
-    g.ldb = ov;
+    g.ldb = ldt;
     g.b_kc = false;
     g.C = sig;
     g.ldc = ov;
@@ -494,66 +517,68 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   const int nK = f->naux_k, nok = f->nok, nvk = f->nvk;
   const bool exch = nK > 0 && nok > 0 && nvk > 0;
   if (exch) {
-    {
-      PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0,
-                    (double)m * nok * nvk * (dtype_size(tv) + dtype_size(tc)));
-      gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
-                    f->ws_xw.get(), tc, s);
-    }
+    const int nokp = f->nokp, nvkp = f->nvkp;
     const size_t csz = dtype_size(tc);
-    const int64_t per_p = (int64_t)m * nvk * nok;
+    const int64_t per_p = (int64_t)m * nvk * nokp;
     const int pc = (int)std::min<int64_t>(nK, f->ws_mt.bytes() / (per_p * csz));
     RISP_CHECK(pc >= 1, RISP_E_STATE, "sigma workspace too small for one auxiliary slice");
-    need(f->ws_xw, (size_t)per_p * csz, "Xw");
-    need(f->ws_k, (size_t)per_p * dtype_size(tacc), "K");
+    need(f->ws_xw, (size_t)m * nokp * nvkp * csz, "Xw");
+    need(f->ws_k, (size_t)m * nok * nvk * dtype_size(tacc), "K");
+    {
+      // window block of X, rows and columns padded with zeros ([m][nokp][nvkp])
+      PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0,
+                    (double)m * nok * nvk * dtype_size(tv) + (double)m * nokp * nvkp * csz);
+      gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
+                    f->ws_xw.get(), tc, nokp, nvkp, s);
+    }
     for (int P0 = 0; P0 < nK; P0 += pc) {
       const int np = std::min(pc, nK - P0);
-      // GEMM1: Mt[m][a][(p, j)] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]
+      // GEMM1: Mt[m][a][(p, j)] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]  (j over the padded range)
       std::optional<PhaseScope> ps1(std::in_place, f->ctx, s, RISP_PHASE_EXCHANGE_M,
                                     2.0 * m * np * (double)nvk * nvk * nok,
                                     (double)csz * ((double)np * nvk * nvk + (double)m * nok * nvk +
                                                    (double)m * np * nvk * nok));
       Gemm g1;
       g1.M = nvk;
-      g1.N = nok;
-      g1.K = nvk;
+      g1.N = nokp;
+      g1.K = nvkp;  // the padding columns of T_ab and Xw are zero
       g1.tin = tc;
       g1.tout = tc;
-      g1.A = static_cast<const char*>(Tab) + (size_t)P0 * nvk * nvk * csz;
-      g1.lda = nvk;
+      g1.A = static_cast<const char*>(Tab) + (size_t)P0 * nvk * nvkp * csz;
+      g1.lda = nvkp;
       g1.B = f->ws_xw.get();
-      g1.ldb = nvk;
+      g1.ldb = nvkp;
       g1.C = f->ws_mt.get();
-      g1.ldc = (int64_t)np * nok;
+      g1.ldc = (int64_t)np * nokp;
       g1.nb1 = m;
       g1.nb2 = np;
       g1.sa1 = 0;
-      g1.sa2 = (int64_t)nvk * nvk;
-      g1.sb1 = (int64_t)nok * nvk;
+      g1.sa2 = (int64_t)nvk * nvkp;
+      g1.sb1 = (int64_t)nokp * nvkp;
       g1.sb2 = 0;
-      g1.sc1 = (int64_t)nvk * np * nok;
-      g1.sc2 = nok;
+      g1.sc1 = (int64_t)nvk * np * nokp;
+      g1.sc2 = nokp;
       g1.batch_scale = bf ? f->scale_k.as<float>() + P0 : nullptr;
       gemm(g1, nullptr, s);
       ps1.reset();
-      // GEMM2: K[m][i][a] += sum_(p, j) T_ij[i][(P0 + p) j] Mt[m][a][(p, j)]
+      // GEMM2: K[m][i][a] += sum_(p, j) T_ij[i][(P0 + p) j] Mt[m][a][(p, j)]  (padding terms are zero)
       PhaseScope ps2(f->ctx, s, RISP_PHASE_EXCHANGE_K, 2.0 * m * (double)nok * np * nok * nvk,
                      (double)csz * ((double)nok * np * nok + (double)m * np * nvk * nok) +
                          (double)dtype_size(tacc) * m * nok * nvk * (P0 > 0 ? 2.0 : 1.0));
       Gemm g2;
       g2.M = nok;
       g2.N = nvk;
-      g2.K = np * nok;
+      g2.K = np * nokp;
       g2.tin = tc;
       g2.tout = tacc;
-      g2.A = static_cast<const char*>(Tij) + (size_t)P0 * nok * csz;
-      g2.lda = (int64_t)nK * nok;
+      g2.A = static_cast<const char*>(Tij) + (size_t)P0 * nokp * csz;
+      g2.lda = (int64_t)nK * nokp;
       g2.B = f->ws_mt.get();
-      g2.ldb = (int64_t)np * nok;
+      g2.ldb = (int64_t)np * nokp;
       g2.C = f->ws_k.get();
       g2.ldc = nvk;
       g2.nb2 = m;
-      g2.sb2 = (int64_t)nvk * np * nok;
+      g2.sb2 = (int64_t)nvk * np * nokp;
       g2.sc2 = (int64_t)nok * nvk;
       g2.beta = P0 > 0 ? 1.0 : 0.0;
       gemm(g2, nullptr, s);

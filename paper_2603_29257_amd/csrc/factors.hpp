@@ -57,6 +57,8 @@ struct risp_factors {
   hipStream_t stream = nullptr;  // stream of this object's work (the context stream, or a job stream)
   int nao = 0, nmo = 0, nocc = 0, nvir = 0;
   int naux_j = 0, naux_k = 0, nok = 0, nvk = 0, npair = 0;
+  int64_t ld_ia = 0;     // row stride of T_ia (nocc*nvir padded to a multiple of 8)
+  int nokp = 0, nvkp = 0;  // row strides of T_ij and T_ab (window sizes padded to multiples of 8)
   int precision = RISP_FP32;
   bool has_f32 = false;  // FP32 copies kept next to BF16 factors (correction pass)
   risp::DevBuf t_ia, t_ij, t_ab;           // stored precision

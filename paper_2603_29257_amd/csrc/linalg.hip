@@ -193,6 +193,7 @@ void gather_transpose(const double* C, int64_t ldc, int nao, const int* cols, in
 template <typename TS, typename TD> __device__ __forceinline__ TD cvt(TS v) { return (TD)v; }
 template <> __device__ __forceinline__ uint16_t cvt<double, uint16_t>(double v) { return f2bf_rne((float)v); }
 template <> __device__ __forceinline__ uint16_t cvt<float, uint16_t>(float v) { return f2bf_rne(v); }
+template <> __device__ __forceinline__ uint16_t cvt<uint16_t, uint16_t>(uint16_t v) { return v; }
 
 template <typename TS, typename TD>
 __global__ void k_convert(const TS* __restrict__ a, TD* __restrict__ b, int64_t n) {
@@ -218,10 +219,8 @@ void convert(const void* src, DType ts, void* dst, DType td, int64_t n, hipStrea
   RISP_LAUNCHED();
 }
 
-// one block per row: max |A[r][:]| -> power-of-two scale -> scaled BF16 row
-__global__ __launch_bounds__(256) void k_scale_rows_bf16(const double* __restrict__ A, int64_t cols,
-                                                         float* __restrict__ scale,
-                                                         uint16_t* __restrict__ dst) {
+__global__ __launch_bounds__(256) void k_row_pow2(const double* __restrict__ A, int64_t cols,
+                                                  float* __restrict__ scale) {
   __shared__ double red[256];
   const double* a = A + (int64_t)blockIdx.x * cols;
   double m = 0.0;
@@ -232,23 +231,80 @@ __global__ __launch_bounds__(256) void k_scale_rows_bf16(const double* __restric
     if (threadIdx.x < d) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + d]);
     __syncthreads();
   }
-  const double mx = red[0];
-  double sc = 1.0;
-  if (mx > 0.0) {
-    int e;
-    const double f = frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
-    sc = ldexp(1.0, f == 0.5 ? e - 1 : e);  // smallest power of two >= mx
+  if (threadIdx.x == 0) {
+    const double mx = red[0];
+    double sc = 1.0;
+    if (mx > 0.0) {
+      int e;
+      const double f = frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+      sc = ldexp(1.0, f == 0.5 ? e - 1 : e);  // smallest power of two >= mx
+    }
+    scale[blockIdx.x] = (float)sc;
   }
-  if (threadIdx.x == 0) scale[blockIdx.x] = (float)sc;
-  const double inv = 1.0 / sc;  // exact: sc is a power of two
-  uint16_t* d = dst + (int64_t)blockIdx.x * cols;
-  for (int64_t c = threadIdx.x; c < cols; c += blockDim.x) d[c] = f2bf_rne((float)(a[c] * inv));
 }
 
-void scale_rows_bf16(const double* A, int rows, int64_t cols, float* scale, void* dst, hipStream_t s) {
+void row_pow2_scales(const double* A, int rows, int64_t cols, float* scale, hipStream_t s) {
   if (rows == 0) return;
-  k_scale_rows_bf16<<<rows, 256, 0, s>>>(A, cols, scale, (uint16_t*)dst);
+  k_row_pow2<<<rows, 256, 0, s>>>(A, cols, scale);
   RISP_LAUNCHED();
+}
+
+template <typename TS, typename TD>
+__global__ void k_store_padded(const TS* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
+                               TD* __restrict__ dst, int64_t ldd, const float* __restrict__ scale, int64_t div,
+                               int64_t mod) {
+  const int64_t total = rows * ldd;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / ldd, c = t % ldd;
+    double v = 0.0;
+    if (c < cols) {
+      v = (double)src[r * lds + c];
+      if (scale) v /= (double)scale[(r / div) % mod];  // exact: powers of two
+    }
+    dst[t] = cvt<double, TD>(v);
+  }
+}
+
+void store_rows_padded(const void* src, DType ts, int64_t lds, int64_t rows, int64_t cols, void* dst, DType td,
+                       int64_t ldd, const float* scale, int64_t div, int64_t mod, hipStream_t s) {
+  const int64_t total = rows * ldd;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 18);
+#define RISP_SP(TS_, TD_) \
+  k_store_padded<TS_, TD_><<<grid, 256, 0, s>>>((const TS_*)src, lds, rows, cols, (TD_*)dst, ldd, scale, div, mod)
+  if (ts == DType::F64 && td == DType::F64) RISP_SP(double, double);
+  else if (ts == DType::F64 && td == DType::F32) RISP_SP(double, float);
+  else if (ts == DType::F64 && td == DType::BF16) RISP_SP(double, uint16_t);
+  else if (ts == DType::F32 && td == DType::BF16) RISP_SP(float, uint16_t);
+  else if (ts == DType::F32 && td == DType::F32) RISP_SP(float, float);
+  else throw Error(RISP_E_ARG, "store_rows_padded: unsupported type pair");
+#undef RISP_SP
+  RISP_LAUNCHED();
+}
+
+__global__ void k_fill_zero16(uint4* p, int64_t n16) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n16; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = make_uint4(0, 0, 0, 0);
+}
+__global__ void k_fill_zero1(uint8_t* p, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = 0;
+}
+
+void fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  const int64_t n16 = (reinterpret_cast<uintptr_t>(p) % 16 == 0) ? (int64_t)(bytes / 16) : 0;
+  if (n16 > 0) {
+    k_fill_zero16<<<(unsigned)std::min<int64_t>(ceil_div(n16, 256), 1 << 16), 256, 0, s>>>((uint4*)p, n16);
+    RISP_LAUNCHED();
+  }
+  const int64_t rest = (int64_t)bytes - n16 * 16;
+  if (rest > 0) {
+    k_fill_zero1<<<(unsigned)std::min<int64_t>(ceil_div(rest, 256), 1 << 16), 256, 0, s>>>((uint8_t*)p + n16 * 16,
+                                                                                           rest);
+    RISP_LAUNCHED();
+  }
 }
 
 template <typename T>
@@ -310,28 +366,28 @@ void window_positions(const int* idx, int n, int len, int* pos, hipStream_t s) {
 template <typename TS, typename TD>
 __global__ void k_gather_window(const TS* __restrict__ X, int m, int nocc, int nvir,
                                 const int* __restrict__ occ, int nok, const int* __restrict__ vir,
-                                int nvk, TD* __restrict__ Xw) {
-  const int64_t total = (int64_t)m * nok * nvk;
+                                int nvk, TD* __restrict__ Xw, int nokp, int nvkp) {
+  const int64_t total = (int64_t)m * nokp * nvkp;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int b = (int)(t % nvk);
-    const int j = (int)((t / nvk) % nok);
-    const int mm = (int)(t / ((int64_t)nvk * nok));
-    Xw[t] = cvt<TS, TD>(X[((int64_t)mm * nocc + occ[j]) * nvir + vir[b]]);
+    const int b = (int)(t % nvkp);
+    const int j = (int)((t / nvkp) % nokp);
+    const int mm = (int)(t / ((int64_t)nvkp * nokp));
+    Xw[t] = (j < nok && b < nvk) ? cvt<TS, TD>(X[((int64_t)mm * nocc + occ[j]) * nvir + vir[b]]) : cvt<double, TD>(0.0);
   }
 }
 
 void gather_window(const void* X, DType ts, int m, int nocc, int nvir, const int* occ, int nok,
-                   const int* vir, int nvk, void* Xw, DType td, hipStream_t s) {
-  const int64_t total = (int64_t)m * nok * nvk;
+                   const int* vir, int nvk, void* Xw, DType td, int nokp, int nvkp, hipStream_t s) {
+  const int64_t total = (int64_t)m * nokp * nvkp;
   if (total == 0) return;
   const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
   if (ts == DType::F64 && td == DType::F64)
-    k_gather_window<double, double><<<grid, 256, 0, s>>>((const double*)X, m, nocc, nvir, occ, nok, vir, nvk, (double*)Xw);
+    k_gather_window<double, double><<<grid, 256, 0, s>>>((const double*)X, m, nocc, nvir, occ, nok, vir, nvk, (double*)Xw, nokp, nvkp);
   else if (ts == DType::F32 && td == DType::F32)
-    k_gather_window<float, float><<<grid, 256, 0, s>>>((const float*)X, m, nocc, nvir, occ, nok, vir, nvk, (float*)Xw);
+    k_gather_window<float, float><<<grid, 256, 0, s>>>((const float*)X, m, nocc, nvir, occ, nok, vir, nvk, (float*)Xw, nokp, nvkp);
   else if (ts == DType::F32 && td == DType::BF16)
-    k_gather_window<float, uint16_t><<<grid, 256, 0, s>>>((const float*)X, m, nocc, nvir, occ, nok, vir, nvk, (uint16_t*)Xw);
+    k_gather_window<float, uint16_t><<<grid, 256, 0, s>>>((const float*)X, m, nocc, nvir, occ, nok, vir, nvk, (uint16_t*)Xw, nokp, nvkp);
   else
     throw Error(RISP_E_ARG, "gather_window: unsupported type pair");
   RISP_LAUNCHED();

@@ -20,9 +20,18 @@ void gather_transpose(const double* C, int64_t ldc, int nao, const int* cols, in
 // dst[i] = (type) src[i] (FP64/FP32 -> FP64/FP32/BF16), n elements.
 void convert(const void* src, DType ts, void* dst, DType td, int64_t n, hipStream_t s);
 
-// Per-row power-of-two scales s_r = 2^ceil(log2 max_c |A[r][c]|) (1 for a zero row) of an FP64
-// matrix [rows][cols], then dst[r][c] = bf16(A[r][c] / s_r); scale[r] = s_r.
-void scale_rows_bf16(const double* A, int rows, int64_t cols, float* scale, void* dst, hipStream_t s);
+// zero `bytes` bytes with a kernel (safe inside graph capture, unlike a memset node)
+void fill_zero(void* p, size_t bytes, hipStream_t s);
+
+// scale[r] = 2^ceil(log2 max_c |A[r][c]|) (1 for a zero row) of an FP64 matrix [rows][cols]
+void row_pow2_scales(const double* A, int rows, int64_t cols, float* scale, hipStream_t s);
+
+// dst[r][c] = (td)(src[r][c] / scale[(r / div) % mod]) for c < cols and 0 for cols <= c < ldd;
+// src is FP64 or FP32 [rows][lds]; scale may be null (no scaling).
+void store_rows_padded(const void* src, DType ts, int64_t lds, int64_t rows, int64_t cols, void* dst, DType td,
+                       int64_t ldd, const float* scale, int64_t div, int64_t mod, hipStream_t s);
+
+inline int64_t pad8(int64_t n) { return (n + 7) / 8 * 8; }
 
 // T [P][i][j] -> out [i][P][j]  (element size esz bytes)
 void permute_pij_ipj(const void* T, int nP, int ni, int nj, size_t esz, void* out, hipStream_t s);
@@ -33,9 +42,10 @@ void orbital_gaps(const double* e, int nocc, int nvir, double* de64, float* de32
 // window position maps: pos[k] = index of k in idx[0..n) or -1 (length len)
 void window_positions(const int* idx, int n, int len, int* pos, hipStream_t s);
 
-// Xw[m][j][b] = X[m][occ[j]][vir[b]] with conversion from ts to td
+// Xw[m][j][b] = X[m][occ[j]][vir[b]] with conversion from ts to td for j < nok, b < nvk; Xw is
+// [m][nokp][nvkp] and its padding (j >= nok or b >= nvk) is written with zeros
 void gather_window(const void* X, DType ts, int m, int nocc, int nvir, const int* occ, int nok,
-                   const int* vir, int nvk, void* Xw, DType td, hipStream_t s);
+                   const int* vir, int nvk, void* Xw, DType td, int nokp, int nvkp, hipStream_t s);
 
 // sigma[m][i][a] += de[i][a] X[m][i][a] - (i, a in window ? K[m][pos_o[i]][pos_v[a]] : 0)
 void combine_sigma(void* sigma, const void* X, DType t, const double* de64, const float* de32, int m,

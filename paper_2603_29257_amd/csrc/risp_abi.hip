@@ -299,6 +299,9 @@ risp_status risp_factors_query(const risp_factors* f, risp_factors_desc* d) {
     d->scale_k = (f->precision == RISP_BF16 && f->naux_k) ? f->scale_k.as<float>() : nullptr;
     d->occ_k = f->occ_k.as<int32_t>();
     d->vir_k = f->vir_k.as<int32_t>();
+    d->ld_ia = f->ld_ia;
+    d->ld_ij = f->nokp;
+    d->ld_ab = f->nvkp;
     return RISP_OK;
   });
 }

@@ -162,6 +162,14 @@ def test_factors_fp32_and_bf16_storage(ctx, mol0, oracle0):
     err = np.abs(Tia - oracle0.B_ia).max() / np.abs(oracle0.B_ia).max()
     _print(f"T_ia BF16 max rel err {err:.3e}")
     assert err <= 2 ** -8
+    # stored rows are padded to 8 elements (16 bytes) with zeros
+    d = F.desc
+    assert d.ld_ia % 8 == 0 and d.ld_ia - 8 < d.nocc * d.nvir <= d.ld_ia
+    assert d.ld_ij % 8 == 0 and d.ld_ij - 8 < d.nocc_k <= d.ld_ij
+    assert d.ld_ab % 8 == 0 and d.ld_ab - 8 < d.nvir_k <= d.ld_ab
+    for name, n in (("t_ia", d.nocc * d.nvir), ("t_ij", d.nocc_k), ("t_ab", d.nvir_k)):
+        full = F.tensor(name, padded=True).float().cpu().numpy()
+        assert np.all(full[..., n:] == 0), name
     F.free()
 
 
