@@ -399,6 +399,8 @@ double sigma_flops(const risp_factors* f, int m) {
 }
 
 constexpr int kMaxSplit = 1024;
+constexpr int kMaxSplitK = 4;                 // split-K of the second exchange product
+constexpr int64_t kMtBudget = 4ll << 30;      // bytes of the exchange intermediate per P-chunk
 
 // Workspaces are sized for the largest block and the widest compute type seen so far (BF16
 // factors also run FP32 products in the correction pass).
@@ -412,15 +414,17 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   f->ws_y.alloc((size_t)f->naux_j * m * acc);
   f->ws_ybf.alloc((size_t)f->naux_j * m * 2 + 16);
   f->ws_xbf.alloc((size_t)m * f->ld_ia * 2 + 16);
-  f->ws_split.alloc((size_t)kMaxSplit * f->naux_j * m * acc);
+  size_t split_bytes = (size_t)kMaxSplit * f->naux_j * m * acc;
   if (f->naux_k > 0 && f->nok > 0 && f->nvk > 0) {
     const int64_t per_p = (int64_t)m * f->nvk * f->nokp;
-    // P-chunk: intermediate M at most ~1 GiB and at least one slice
-    const int64_t pc = std::max<int64_t>(1, std::min<int64_t>(f->naux_k, (1ll << 30) / (per_p * cs)));
+    // P-chunk: intermediate at most kMtBudget bytes and at least one auxiliary function
+    const int64_t pc = std::max<int64_t>(1, std::min<int64_t>(f->naux_k, kMtBudget / (per_p * cs)));
     f->ws_xw.alloc((size_t)m * f->nokp * f->nvkp * cs);
     f->ws_mt.alloc((size_t)per_p * pc * cs);
     f->ws_k.alloc((size_t)m * f->nok * f->nvk * acc);
+    split_bytes = std::max(split_bytes, (size_t)kMaxSplitK * m * f->nok * f->nvk * acc);
   }
+  f->ws_split.alloc(split_bytes);
   f->ws_m = m;
   f->ws_csz = cs;
 }
@@ -533,14 +537,15 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
     }
     for (int P0 = 0; P0 < nK; P0 += pc) {
       const int np = std::min(pc, nK - P0);
-      // GEMM1: Mt[m][a][(p, j)] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]  (j over the padded range)
+      // product 1, one GEMM per auxiliary function P over all trial vectors at once:
+      //   Mt[m][a][p][j] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]   (rows a, columns (m, j))
       std::optional<PhaseScope> ps1(std::in_place, f->ctx, s, RISP_PHASE_EXCHANGE_M,
                                     2.0 * m * np * (double)nvk * nvk * nok,
                                     (double)csz * ((double)np * nvk * nvk + (double)m * nok * nvk +
                                                    (double)m * np * nvk * nok));
       Gemm g1;
       g1.M = nvk;
-      g1.N = nokp;
+      g1.N = m * nokp;
       g1.K = nvkp;  // the padding columns of T_ab and Xw are zero
       g1.tin = tc;
       g1.tout = tc;
@@ -550,24 +555,22 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g1.ldb = nvkp;
       g1.C = f->ws_mt.get();
       g1.ldc = (int64_t)np * nokp;
-      g1.nb1 = m;
       g1.nb2 = np;
-      g1.sa1 = 0;
       g1.sa2 = (int64_t)nvk * nvkp;
-      g1.sb1 = (int64_t)nokp * nvkp;
-      g1.sb2 = 0;
-      g1.sc1 = (int64_t)nvk * np * nokp;
       g1.sc2 = nokp;
+      g1.n_inner = nokp;
+      g1.sc_outer = (int64_t)nvk * np * nokp;
       g1.batch_scale = bf ? f->scale_k.as<float>() + P0 : nullptr;
       gemm(g1, nullptr, s);
       ps1.reset();
-      // GEMM2: K[m][i][a] += sum_(p, j) T_ij[i][(P0 + p) j] Mt[m][a][(p, j)]  (padding terms are zero)
+      // product 2, one GEMM over the chunk: K[m][i][a] (+)= sum_(p, j) T_ij[i][P0 + p][j] Mt[m][a][p][j]
+      // (rows i, columns (m, a); padding terms are zero)
       PhaseScope ps2(f->ctx, s, RISP_PHASE_EXCHANGE_K, 2.0 * m * (double)nok * np * nok * nvk,
                      (double)csz * ((double)nok * np * nok + (double)m * np * nvk * nok) +
                          (double)dtype_size(tacc) * m * nok * nvk * (P0 > 0 ? 2.0 : 1.0));
       Gemm g2;
       g2.M = nok;
-      g2.N = nvk;
+      g2.N = m * nvk;
       g2.K = np * nokp;
       g2.tin = tc;
       g2.tout = tacc;
@@ -577,11 +580,13 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g2.ldb = (int64_t)np * nokp;
       g2.C = f->ws_k.get();
       g2.ldc = nvk;
-      g2.nb2 = m;
-      g2.sb2 = (int64_t)nvk * np * nokp;
-      g2.sc2 = (int64_t)nok * nvk;
+      g2.n_inner = nvk;
+      g2.sc_outer = (int64_t)nok * nvk;
       g2.beta = P0 > 0 ? 1.0 : 0.0;
-      gemm(g2, nullptr, s);
+      const int64_t per_split = (int64_t)g2.M * g2.N * (int64_t)dtype_size(tacc);
+      g2.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kMaxSplitK, (int64_t)gemm_auto_split(g2),
+                                                               (int64_t)f->ws_split.bytes() / per_split}));
+      gemm(g2, g2.ksplit > 1 ? f->ws_split.get() : nullptr, s);
     }
   }
   PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, (double)m * ov * 3.0,

@@ -39,6 +39,12 @@ template <> struct MF<bfs> {
 
 template <typename T> __device__ __forceinline__ T zero_val() { return T(0); }
 
+// element offset of output column `col` within its row (see Gemm::n_inner)
+__device__ __forceinline__ int64_t col_offset(const Gemm& g, int col) {
+  if (g.n_inner <= 0) return col;
+  return (int64_t)(col / g.n_inner) * g.sc_outer + col % g.n_inner;
+}
+
 template <typename TO> __device__ __forceinline__ TO to_out(double v);
 template <> __device__ __forceinline__ double to_out<double>(double v) { return v; }
 template <> __device__ __forceinline__ float to_out<float>(double v) { return (float)v; }
@@ -243,7 +249,7 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g, int batch0, void* __restri
         if (row < g.M && col < g.N) {
           double v = g.alpha * bs * (double)acc[i][j][r];
           if (g.row_scale) v *= (double)g.row_scale[row];
-          TO* cp = C + (int64_t)row * g.ldc + col;
+          TO* cp = C + (int64_t)row * g.ldc + col_offset(g, col);
           if (g.beta != 0.0) v += g.beta * from_out<TO>(*cp);
           *cp = to_out<TO>(v);
         }
@@ -266,7 +272,7 @@ __global__ void k_gemm_reduce(Gemm g, const Acc* __restrict__ work, int nbatch) 
     double v = g.alpha * (double)s;
     if (g.batch_scale) v *= (double)g.batch_scale[b2];
     if (g.row_scale) v *= (double)g.row_scale[row];
-    TO* cp = static_cast<TO*>(g.C) + b1 * g.sc1 + b2 * g.sc2 + (int64_t)row * g.ldc + col;
+    TO* cp = static_cast<TO*>(g.C) + b1 * g.sc1 + b2 * g.sc2 + (int64_t)row * g.ldc + col_offset(g, col);
     if (g.beta != 0.0) v += g.beta * from_out<TO>(*cp);
     *cp = to_out<TO>(v);
   }
@@ -291,6 +297,17 @@ size_t gemm_workspace_bytes(const Gemm& g) {
 
 int gemm_auto_split(const Gemm& g) {
   const bool f64 = g.tin == DType::F64;
+  if (gemm_bf16_nt_eligible(g)) {
+    // large tiles, one block per CU: aim for at least four waves of blocks over 256 CUs
+    Gemm h = g;
+    h.ksplit = 1;
+    const int bm = gemm_bf16_nt_tile(h);
+    const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + 255) / 256) * g.nb1 * g.nb2;
+    if (tiles >= 1024) return 1;
+    int64_t split = (1024 + tiles - 1) / tiles;
+    split = std::min<int64_t>(split, std::max(1, g.K / (8 * 64)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(split, 4096));
+  }
   const int bm = f64 ? 64 : 128, bn = bm;
   const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.nb1 * g.nb2;
   if (tiles >= 1024) return 1;

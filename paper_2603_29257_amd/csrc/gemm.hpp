@@ -39,6 +39,10 @@ struct Gemm {
   const float* row_scale = nullptr;
   const float* batch_scale = nullptr;
   int ksplit = 1;  // > 1 splits K over blocks (uses workspace)
+  // column split of C: when n_inner > 0, column n is stored at (n / n_inner) * sc_outer + n % n_inner
+  // within its row (lets one product write an interleaved [outer][row][inner] layout)
+  int n_inner = 0;
+  int64_t sc_outer = 0;
 };
 
 // Launch on stream s. `work` must hold ksplit * nb1 * nb2 * M * N accumulator elements when
@@ -46,12 +50,14 @@ struct Gemm {
 size_t gemm_workspace_bytes(const Gemm& g);
 void gemm(const Gemm& g, void* work, hipStream_t s);
 
-// Tuned BF16 kernel for contraction-contiguous operands (used by gemm() when eligible).
+// Tuned BF16 kernel for contraction-contiguous operands (used by gemm() when eligible: BF16
+// products, F32/BF16 output, 16-byte aligned operands, strides and K multiples of 8).
 bool gemm_bf16_nt_eligible(const Gemm& g);
+int gemm_bf16_nt_tile(const Gemm& g);  // rows of the output tile it would use (128, 192, 256)
 void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s);
 
-// Choose a split-K factor so that the grid covers the chip (about 2048 blocks) for skinny
-// products; returns 1 when tiles alone suffice.
+// Choose a split-K factor so that the grid covers the chip for products with few output tiles;
+// returns 1 when tiles alone suffice.
 int gemm_auto_split(const Gemm& g);
 
 }  // namespace risp

@@ -1,7 +1,15 @@
 // BF16 products with both operands stored contraction-contiguous (C = A . B^T), the form of the
-// exchange and Coulomb-Y products of sigma. 128 x 256 output tile per 256-thread block (4 wave64s,
-// each 64 x 128 with v_mfma_f32_32x32x16_bf16), K in slices of 64 staged through LDS; the next
-// slice's global loads are issued before the current slice's MFMAs so their latency is hidden.
+// exchange and Coulomb products of sigma.
+//
+// One 256-thread block (4 wave64s, 2 x 2) computes a BM x 256 tile, BM = 64 * TI (128, 192 or
+// 256); each wave owns a (BM/2) x 128 sub-tile of TI x 4 v_mfma_f32_32x32x16_bf16 accumulators.
+// K advances in slices of 64 through two LDS stages: while the MFMAs consume one stage, the next
+// slice (already in registers) is written to the other stage and the slice after it is requested
+// from memory, so one barrier per slice suffices. LDS rows are 128 bytes with the 16-byte chunks
+// XOR-swizzled by (row / 2) mod 8, which makes both the 16-byte fragment reads of an MFMA and the
+// row-slice writes conflict-free without padding. Blocks are renumbered so that consecutive tiles
+// land on the same XCD (the dispatcher deals workgroups round-robin over the 8 XCDs), which lets
+// neighbouring tiles share operand panels in that XCD's L2.
 #include "gemm.hpp"
 
 namespace risp {
@@ -11,7 +19,7 @@ namespace {
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 128, BN = 256, BK = 64, LDK = BK + 8;  // LDS row stride in elements (144 bytes)
+constexpr int BN = 256, BK = 64, ROWB = 128;  // tile width, K slice, LDS bytes per row
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -20,53 +28,44 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-template <typename TO> __device__ __forceinline__ void store_out(TO* p, double v);
-template <> __device__ __forceinline__ void store_out<float>(float* p, double v) { *p = (float)v; }
-template <> __device__ __forceinline__ void store_out<uint16_t>(uint16_t* p, double v) { *p = f2bf((float)v); }
-template <typename TO> __device__ __forceinline__ double load_out(const TO* p);
-template <> __device__ __forceinline__ double load_out<float>(const float* p) { return *p; }
-template <> __device__ __forceinline__ double load_out<uint16_t>(const uint16_t* p) { return bf2f(*p); }
+template <typename TO> __device__ __forceinline__ void store_out(TO* p, float v);
+template <> __device__ __forceinline__ void store_out<float>(float* p, float v) { *p = v; }
+template <> __device__ __forceinline__ void store_out<uint16_t>(uint16_t* p, float v) { *p = f2bf(v); }
+template <typename TO> __device__ __forceinline__ float load_out(const TO* p);
+template <> __device__ __forceinline__ float load_out<float>(const float* p) { return *p; }
+template <> __device__ __forceinline__ float load_out<uint16_t>(const uint16_t* p) { return bf2f(*p); }
 
-// rows x 64 slice starting at (r0, k0) of a k-contiguous BF16 operand into registers (16-byte
-// vectors; out-of-range elements are zero)
-template <int ROWS>
-__device__ __forceinline__ void gload(uint4 (&r)[ROWS / 32], const uint16_t* __restrict__ src, int64_t ld,
-                                      int nrows, int kend, int r0, int k0) {
-#pragma unroll
-  for (int q = 0; q < ROWS / 32; ++q) {
-    const int v = threadIdx.x + 256 * q;
-    const int row = v >> 3, kv = (v & 7) * 8;
-    const int gr = r0 + row, gk = k0 + kv;
-    if (gr < nrows && gk + 8 <= kend) {
-      r[q] = *reinterpret_cast<const uint4*>(src + gr * ld + gk);
-    } else {
-      uint16_t t[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) t[e] = (gr < nrows && gk + e < kend) ? src[gr * ld + gk + e] : (uint16_t)0;
-      r[q] = *reinterpret_cast<uint4*>(t);
-    }
-  }
+// element offset of output column `col` (column split: col -> (col / n_inner, col % n_inner))
+__device__ __forceinline__ int64_t col_offset(const Gemm& g, int col) {
+  if (g.n_inner <= 0) return col;
+  return (int64_t)(col / g.n_inner) * g.sc_outer + col % g.n_inner;
 }
 
-template <int ROWS>
-__device__ __forceinline__ void sstore(uint16_t* lds, const uint4 (&r)[ROWS / 32]) {
-#pragma unroll
-  for (int q = 0; q < ROWS / 32; ++q) {
-    const int v = threadIdx.x + 256 * q;
-    const int row = v >> 3, kv = (v & 7) * 8;
-    *reinterpret_cast<uint4*>(lds + row * LDK + kv) = r[q];
-  }
+// raw buffer descriptor (stride 0, num_records bytes); the fields are made wave-uniform so the
+// descriptor lives in scalar registers
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const int n = __builtin_amdgcn_readfirstlane(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, n,
+                                           0x00020000);
 }
 
-template <typename TO>
-__global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int batch0, float* __restrict__ work) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
-  const int tiles_m = (g.M + BM - 1) / BM;
-  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-  const int zb = blockIdx.y + batch0;
-  const int split = zb % g.ksplit;
-  const int b = zb / g.ksplit;
+template <int TI, typename TO>
+__global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, int tiles_n,
+                                                         float* __restrict__ work) {
+  constexpr int BM = 64 * TI, ROWS = BM + BN, NLD = ROWS / 32, STAGE = ROWS * ROWB;
+  __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
+
+  // XCD-aware renumbering: hardware block w runs on XCD w % 8; logical tiles L are contiguous per XCD
+  const int W = gridDim.x, w = blockIdx.x;
+  const int per = (W + 7) / 8, tall = (W % 8 == 0) ? 8 : W % 8, x = w % 8, q = w / 8;
+  const int L = x < tall ? x * per + q : tall * per + (x - tall) * (per - 1) + q;
+  const int tiles = tiles_m * tiles_n;
+  const int zb = L / tiles, t = L % tiles;
+  const int tm = t % tiles_m, tn = t / tiles_m;
+  const int split = zb % g.ksplit, b = zb / g.ksplit;
   const int b1 = b / g.nb2, b2 = b % g.nb2;
   const uint16_t* A = static_cast<const uint16_t*>(g.A) + b1 * g.sa1 + b2 * g.sa2;
   const uint16_t* B = static_cast<const uint16_t*>(g.B) + b1 * g.sb1 + b2 * g.sb2;
@@ -77,85 +76,136 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int batch0, flo
     kbeg = split * kchunk;
     kend = min(g.K, kbeg + kchunk);
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 128;
-  f16v acc[2][4];
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+
+  // loader: thread loads 16-byte chunk c_t of rows r_t + 32 q (q < NLD; the first BM / 32 are A
+  // rows) through buffer descriptors limited to the tile's valid rows, so rows past M or N and
+  // chunks past K (offset forced out of range) read as zero without branches
+  const int tid = threadIdx.x;
+  const int r_t = tid >> 3, c_t = tid & 7;
+  const int st_off = r_t * ROWB + 16 * (c_t ^ ((r_t >> 1) & 7));  // + q * 32 * ROWB
+  const int rows_a = max(0, min(BM, g.M - m0)), rows_b = max(0, min(BN, g.N - n0));
+  const __amdgpu_buffer_rsrc_t ra =
+      make_rsrc(A + (int64_t)m0 * g.lda, (int)((int64_t)rows_a * g.lda * 2));
+  const __amdgpu_buffer_rsrc_t rb =
+      make_rsrc(B + (int64_t)n0 * g.ldb, (int)((int64_t)rows_b * g.ldb * 2));
+  const uint32_t va = (uint32_t)((r_t * g.lda + 8 * c_t) * 2), vb = (uint32_t)((r_t * g.ldb + 8 * c_t) * 2);
+  const uint32_t qa = (uint32_t)(32 * g.lda * 2), qb = (uint32_t)(32 * g.ldb * 2);
+
+  uint4 reg[NLD];
+  auto gload = [&](int kt) {
+    const int k0 = kbeg + kt * BK;
+    const bool kin = k0 + 8 * c_t < kend;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int qq = 0; qq < NLD; ++qq) {
+      const bool isA = qq < BM / 32;
+      const uint32_t off = isA ? va + qq * qa + 2 * k0 : vb + (qq - BM / 32) * qb + 2 * k0;
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(isA ? ra : rb, kin ? off : 0x80000000u, 0, 0);
+      __builtin_memcpy(&reg[qq], &v, 16);
+    }
+  };
+  auto sstore = [&](int stage) {
+    char* base = lds + stage * STAGE + st_off;
+#pragma unroll
+    for (int qq = 0; qq < NLD; ++qq) *reinterpret_cast<uint4*>(base + qq * 32 * ROWB) = reg[qq];
+  };
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * 128;
+  const int lr = lane & 31, hi = lane >> 5, swz = (lr >> 1) & 7;
+  const int a_off = (wm + lr) * ROWB, b_off = (BM + wn + lr) * ROWB;
+
+  f16v acc[TI][4];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  uint4 ra[BM / 32], rb[BN / 32];
-  if (kbeg < kend) {
-    gload<BM>(ra, A, g.lda, g.M, kend, m0, kbeg);
-    gload<BN>(rb, B, g.ldb, g.N, kend, n0, kbeg);
-    sstore<BM>(As, ra);
-    sstore<BN>(Bs, rb);
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+    if (nk > 1) gload(1);
   }
   __syncthreads();
-  const int lr = lane & 31, lk = 8 * (lane >> 5);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) {
-      gload<BM>(ra, A, g.lda, g.M, kend, m0, k0 + BK);
-      gload<BN>(rb, B, g.ldb, g.N, kend, n0, k0 + BK);
-    }
+  for (int kt = 0; kt < nk; ++kt) {
+    const char* buf = lds + (kt & 1) * STAGE;
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      bf8v a[2], bb[4];
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      const int chunk = 16 * ((2 * ks + hi) ^ swz);
+      bf8v a[TI], bb[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf8v*>(As + (wm + i * 32 + lr) * LDK + ks + lk);
+      for (int i = 0; i < TI; ++i) a[i] = *reinterpret_cast<const bf8v*>(buf + a_off + i * 32 * ROWB + chunk);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = *reinterpret_cast<const bf8v*>(Bs + (wn + j * 32 + lr) * LDK + ks + lk);
+      for (int j = 0; j < 4; ++j) bb[j] = *reinterpret_cast<const bf8v*>(buf + b_off + j * 32 * ROWB + chunk);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
-    if (more) {
-      __syncthreads();
-      sstore<BM>(As, ra);
-      sstore<BN>(Bs, rb);
-      __syncthreads();
-    }
+    if (kt + 1 < nk) sstore((kt + 1) & 1);  // that stage was last read before the previous barrier
+    if (kt + 2 < nk) gload(kt + 2);
+    __syncthreads();
   }
 
+  // accumulator element r of lane l: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
   if (g.ksplit > 1) {
-    float* W = work + ((int64_t)b * g.ksplit + split) * g.M * g.N;
+    float* Wp = work + ((int64_t)b * g.ksplit + split) * g.M * g.N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+        if (row >= g.M) continue;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        for (int j = 0; j < 4; ++j) {
           const int col = n0 + wn + j * 32 + lr;
-          if (row < g.M && col < g.N) W[(int64_t)row * g.N + col] = acc[i][j][r];
+          if (col < g.N) Wp[(int64_t)row * g.N + col] = acc[i][j][r];
         }
+      }
     return;
   }
   TO* C = static_cast<TO*>(g.C) + b1 * g.sc1 + b2 * g.sc2;
-  const double bs = g.alpha * (g.batch_scale ? (double)g.batch_scale[b2] : 1.0);
+  const float bs = (float)g.alpha * (g.batch_scale ? g.batch_scale[b2] : 1.f);
+  const float beta = (float)g.beta;
+  int64_t coff[4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < 4; ++j) {
+    const int col = n0 + wn + j * 32 + lr;
+    coff[j] = col < g.N ? col_offset(g, col) : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
       if (row >= g.M) continue;
-      const double rs = g.row_scale ? bs * (double)g.row_scale[row] : bs;
+      const float rs = g.row_scale ? bs * g.row_scale[row] : bs;
+      TO* crow = C + (int64_t)row * g.ldc;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int col = n0 + wn + j * 32 + lr;
-        if (col < g.N) {
-          TO* cp = C + (int64_t)row * g.ldc + col;
-          double v = rs * (double)acc[i][j][r];
-          if (g.beta != 0.0) v += g.beta * load_out<TO>(cp);
-          store_out<TO>(cp, v);
-        }
+        if (coff[j] < 0) continue;
+        TO* cp = crow + coff[j];
+        float v = rs * acc[i][j][r];
+        if (beta != 0.f) v += beta * load_out<TO>(cp);
+        store_out<TO>(cp, v);
       }
     }
+}
+
+template <int TI>
+void launch_ti(const Gemm& g, void* work, hipStream_t s) {
+  constexpr int BM = 64 * TI;
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const int64_t nz = (int64_t)g.nb1 * g.nb2 * g.ksplit;
+  const int64_t blocks = (int64_t)tm * tn * nz;
+  RISP_CHECK(blocks < (1ll << 31), RISP_E_SHAPE, "gemm grid too large");
+  if (g.tout == DType::F32)
+    k_gemm_bf16_nt<TI, float><<<(unsigned)blocks, 256, 0, s>>>(g, tm, tn, static_cast<float*>(work));
+  else
+    k_gemm_bf16_nt<TI, uint16_t><<<(unsigned)blocks, 256, 0, s>>>(g, tm, tn, static_cast<float*>(work));
+  RISP_LAUNCHED();
 }
 
 }  // namespace
@@ -163,22 +213,42 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int batch0, flo
 bool gemm_bf16_nt_eligible(const Gemm& g) {
   const bool aligned = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0);
   const bool strides = g.lda % 8 == 0 && g.ldb % 8 == 0 && g.sa1 % 8 == 0 && g.sa2 % 8 == 0 &&
-                       g.sb1 % 8 == 0 && g.sb2 % 8 == 0;
-  return g.tin == DType::BF16 && g.a_kc && g.b_kc && aligned && strides &&
+                       g.sb1 % 8 == 0 && g.sb2 % 8 == 0 && g.K % 8 == 0;
+  // buffer offsets within one tile (256 rows) stay below 2^31 bytes
+  const bool small = (int64_t)BN * g.lda * 2 < (1ll << 31) && (int64_t)BN * g.ldb * 2 < (1ll << 31) &&
+                     g.K <= g.lda && g.K <= g.ldb;
+  return g.tin == DType::BF16 && g.a_kc && g.b_kc && aligned && strides && small &&
          (g.tout == DType::F32 || g.tout == DType::BF16);
 }
 
-void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s) {
-  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+int gemm_bf16_nt_tile(const Gemm& g) {
+  // pick BM in {256, 192, 128}: fraction of useful rows x fill of the last wave of blocks x
+  // relative per-tile throughput of the narrower tiles (fewer MFMAs per LDS byte)
   const int64_t nz = (int64_t)g.nb1 * g.nb2 * g.ksplit;
-  RISP_CHECK((int64_t)tm * tn < (1ll << 31), RISP_E_SHAPE, "gemm grid too large");
-  for (int64_t z0 = 0; z0 < nz; z0 += 65535) {
-    const unsigned zc = (unsigned)std::min<int64_t>(65535, nz - z0);
-    if (g.tout == DType::F32)
-      k_gemm_bf16_nt<float><<<dim3(tm * tn, zc), 256, 0, s>>>(g, (int)z0, static_cast<float*>(work));
-    else
-      k_gemm_bf16_nt<uint16_t><<<dim3(tm * tn, zc), 256, 0, s>>>(g, (int)z0, static_cast<float*>(work));
-    RISP_LAUNCHED();
+  const int64_t tn = (g.N + BN - 1) / BN;
+  double best = -1.0;
+  int best_ti = 4;
+  for (int ti = 4; ti >= 2; --ti) {
+    const int bm = 64 * ti;
+    const int64_t tm = (g.M + bm - 1) / bm;
+    const int64_t blocks = tm * tn * nz;
+    const double rows = (double)g.M / (double)(tm * bm);
+    const double fill = (double)blocks / (double)(((blocks + 255) / 256) * 256);
+    const double speed = ti == 4 ? 1.0 : (ti == 3 ? 0.94 : 0.82);
+    const double score = rows * fill * speed;
+    if (score > best + 1e-9) {
+      best = score;
+      best_ti = ti;
+    }
+  }
+  return 64 * best_ti;
+}
+
+void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s) {
+  switch (gemm_bf16_nt_tile(g)) {
+    case 256: launch_ti<4>(g, work, s); break;
+    case 192: launch_ti<3>(g, work, s); break;
+    default: launch_ti<2>(g, work, s); break;
   }
 }
 
