@@ -218,7 +218,7 @@ def main():
 
     b = res["bf16"]
     # dominant kernel of the BF16 sigma blocks: the exchange product M = T_ab X (one launch per chunk)
-    ph = b["prof"]["exchange_m"]
+    ph = b["prof"]["bf16"]["exchange_m"]
     per_launch_ms = ph["ms"] / max(ph["launches"], 1)
     per_launch_flops = ph["flops"] / max(ph["launches"], 1)
     achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
@@ -226,10 +226,13 @@ def main():
                 "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"],
                 "traffic": None, "launches": ph["launches"], "avg_launch_ms": per_launch_ms,
                 "flops_per_launch": per_launch_flops}
-    phases = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                  "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0,
-                  "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
-              for k, v in b["prof"].items()}
+    def phase_table(pr):
+        return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                    "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0,
+                    "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
+                for k, v in pr.items() if v["launches"] > 0}
+    phases = phase_table(b["prof"]["bf16"])
+    phases_corr = phase_table(b["prof"]["fp32"])
     d = b["desc"]
     out = {
         "metric": "time-to-15-states & sigma-build TFLOP/s, BF16 vs plain FP32; p50/p99 latency",
@@ -248,6 +251,7 @@ def main():
         "breakdown_s": {p: {"build": res[p]["t_build"], "sigma": res[p]["t_sigma"], "subspace": res[p]["t_subspace"],
                             "correction": res[p]["t_correct"]} for p in res},
         "phases_bf16": phases,
+        "phases_bf16_job_fp32_correction": phases_corr,
         "roofline": roofline,
         "latency": None if jobs is None else serving_bench(jobs, tol=args.tol),
         "generator_s": t_gen,

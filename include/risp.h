@@ -148,7 +148,11 @@ enum {
   RISP_PHASE_EXCHANGE_M = 2,/* M^P_mja = sum_b T_ab^P X_mjb, one launch per auxiliary chunk */
   RISP_PHASE_EXCHANGE_K = 3,/* K_mia += sum_(P, j) T_ij^P M^P_mja, one launch per auxiliary chunk */
   RISP_PHASE_OTHER = 4,     /* window gather, conversions, diagonal term and combine */
-  RISP_NPHASE = 5
+  RISP_NPHASE = 5,
+  /* counters are kept per arithmetic of the sigma call: slot = precision * RISP_NPHASE + phase,
+   * precision RISP_FP64 / RISP_FP32 / RISP_BF16 (the FP32 correction pass of BF16 factors counts
+   * as RISP_FP32) */
+  RISP_NPHASE_SLOTS = 15
 };
 typedef struct {
   int64_t launches; /* timed launches (or launch groups) */
@@ -169,7 +173,7 @@ risp_status risp_ctx_create(int32_t device, void *hip_stream, risp_ctx **out);
 risp_status risp_ctx_destroy(risp_ctx *ctx);
 
 /* Enable (1) or disable (0) sigma phase timing; reset != 0 clears the counters. If out is not
- * NULL it receives RISP_NPHASE entries (the stream is synchronised first). */
+ * NULL it receives RISP_NPHASE_SLOTS entries (the stream is synchronised first). */
 risp_status risp_ctx_profile(risp_ctx *ctx, int32_t enable, int32_t reset, risp_phase_stat *out);
 
 /* ---- stages of the factor build (exposed for validation; risp_build_factors runs them all) ---- */

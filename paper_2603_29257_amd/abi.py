@@ -323,11 +323,17 @@ class Context:
         self.stream.synchronize()
 
     def profile(self, enable=True, reset=False):
-        """Switch sigma phase timing; returns the counters accumulated so far as a dict."""
-        arr = (PhaseStatC * len(PHASES))()
+        """Switch sigma phase timing; returns the counters accumulated so far as
+        {arithmetic: {phase: counters}} with arithmetic "fp64", "fp32" or "bf16"."""
+        arr = (PhaseStatC * (len(PHASES) * 3))()
         _check(_LIB.risp_ctx_profile(self.handle, int(enable), int(reset), arr))
-        return {name: dict(launches=arr[k].launches, ms=arr[k].ms, flops=arr[k].flops, bytes=arr[k].bytes)
-                for k, name in enumerate(PHASES)}
+        out = {}
+        for prec, name_p in ((FP64, "fp64"), (FP32, "fp32"), (BF16, "bf16")):
+            base = prec * len(PHASES)
+            out[name_p] = {name: dict(launches=arr[base + k].launches, ms=arr[base + k].ms,
+                                      flops=arr[base + k].flops, bytes=arr[base + k].bytes)
+                           for k, name in enumerate(PHASES)}
+        return out
 
     # ---- stages ----
     def select_aux(self, sys: System, prm: Params):

@@ -87,36 +87,46 @@ __global__ void k_scale_rows(double* T, int nt, int64_t ov, const double* norms)
   }
 }
 
-// Gram-Schmidt in coefficient space on one block: given G = T T^T (nt x nt), build the
+// Gram-Schmidt in coefficient space on one block: given G = T T^T (nt x nt, nt <= 64), build the
 // coefficients Q = Cf T of an orthonormal basis of span(T), dropping vectors whose remaining norm is
 // below drop * (norm of the input vector). Cf is [nt][nt] (rows of kept vectors first), count out.
-__global__ void k_block_mgs(const double* __restrict__ G, int nt, double drop, double* __restrict__ Cf,
-                            int* __restrict__ kept) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One wave: lane i holds component i of the candidate; G and the kept rows sit in LDS.
+__global__ __launch_bounds__(64) void k_block_mgs(const double* __restrict__ G, int nt, double drop,
+                                                  double* __restrict__ Cf, int* __restrict__ kept) {
+  __shared__ double sG[64 * 64];
+  __shared__ double sQ[64 * 64];
+  const int lane = threadIdx.x;
+  for (int t = lane; t < nt * nt; t += 64) sG[t] = G[t];
+  __syncthreads();
+  auto wsum = [](double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+  };
   int nk = 0;
   for (int j = 0; j < nt; ++j) {
-    // candidate c = e_j - sum_q (q . t_j) q,  q . t_j = sum_i Cf[q][i] G[i][j]
-    double c[64];
-    for (int i = 0; i < nt; ++i) c[i] = (i == j) ? 1.0 : 0.0;
+    // candidate c = e_j - sum_q (q . t_j) q,  q . t_j = sum_i Q[q][i] G[i][j]
+    double c = (lane == j) ? 1.0 : 0.0;
+    const double gij = lane < nt ? sG[lane * nt + j] : 0.0;
     for (int q = 0; q < nk; ++q) {
-      double dot = 0.0;
-      for (int i = 0; i < nt; ++i) dot += Cf[q * nt + i] * G[i * nt + j];
-      for (int i = 0; i < nt; ++i) c[i] -= dot * Cf[q * nt + i];
+      const double qi = lane < nt ? sQ[q * 64 + lane] : 0.0;
+      const double dot = wsum(qi * gij);
+      c -= dot * qi;
     }
-    double n2 = 0.0;
-    for (int a = 0; a < nt; ++a) {
-      double s = 0.0;
-      for (int b = 0; b < nt; ++b) s += G[a * nt + b] * c[b];
-      n2 += c[a] * s;
-    }
-    const double tj = sqrt(fmax(G[j * nt + j], 0.0));
+    // |c|^2 in the metric G: sum_a c_a (G c)_a
+    double gc = 0.0;
+    for (int b = 0; b < nt; ++b) gc += (lane < nt ? sG[lane * nt + b] : 0.0) * __shfl(c, b, 64);
+    const double n2 = wsum(lane < nt ? c * gc : 0.0);
+    const double tj = sqrt(fmax(sG[j * nt + j], 0.0));
     const double nn = sqrt(fmax(n2, 0.0));
     if (nn > drop * tj && nn > 0.0) {
-      for (int i = 0; i < nt; ++i) Cf[nk * nt + i] = c[i] / nn;
+      if (lane < nt) sQ[nk * 64 + lane] = c / nn;
       ++nk;
     }
+    __syncthreads();
   }
-  *kept = nk;
+  for (int q = 0; q < nk; ++q)
+    if (lane < nt) Cf[q * nt + lane] = sQ[q * 64 + lane];
+  if (lane == 0) *kept = nk;
 }
 
 // eigenvalue copy for the residual kernel
@@ -299,6 +309,7 @@ void DavidsonRun::combine_rows(const double* Cm, int ldcm, int nsub, int k, cons
 
 // orthonormalise the nt FP64 rows of T within the block (coefficient-space Gram-Schmidt, twice)
 int DavidsonRun::orth_block(int nt) {
+  RISP_CHECK(nt <= 64, RISP_E_ARG, "block orthonormalisation handles at most 64 vectors");
   int nk = nt;
   for (int pass = 0; pass < 2 && nk > 0; ++pass) {
     Gemm g;

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <optional>
 
+#include "coulomb.hpp"
 #include "factors.hpp"
 #include "linalg.hpp"
 
@@ -404,6 +405,8 @@ constexpr int64_t kMtBudget = 4ll << 30;      // bytes of the exchange intermedi
 
 // Workspaces are sized for the largest block and the widest compute type seen so far (BF16
 // factors also run FP32 products in the correction pass).
+static int64_t pad_to(int64_t n, int64_t q) { return (n + q - 1) / q * q; }
+
 static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   const int csz = tc == DType::F64 ? 8 : (tc == DType::F32 ? 4 : 2);
   if (m <= f->ws_m && csz <= f->ws_csz) return;
@@ -412,9 +415,10 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   const int cs = std::max(csz, f->ws_csz);
   const size_t acc = cs == 8 ? 8 : 4;
   f->ws_y.alloc((size_t)f->naux_j * m * acc);
-  f->ws_ybf.alloc((size_t)f->naux_j * m * 2 + 16);
+  f->ws_ybf.alloc((size_t)kCoulombMaxM * pad_to(f->naux_j, 32) * 2 + 16);
   f->ws_xbf.alloc((size_t)m * f->ld_ia * 2 + 16);
-  size_t split_bytes = (size_t)kMaxSplit * f->naux_j * m * acc;
+  size_t split_bytes = std::max((size_t)kMaxSplit * f->naux_j * m * acc,
+                                coulomb_y_workspace(f->naux_j, std::min(m, kCoulombMaxM), f->ld_ia));
   if (f->naux_k > 0 && f->nok > 0 && f->nvk > 0) {
     const int64_t per_p = (int64_t)m * f->nvk * f->nokp;
     // P-chunk: intermediate at most kMtBudget bytes and at least one auxiliary function
@@ -445,6 +449,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
   const DType tv = f->precision == RISP_FP64 ? DType::F64 : DType::F32;  // X / sigma type
   const DType tacc = tc == DType::F64 ? DType::F64 : DType::F32;
+  const int pb = RISP_NPHASE * (bf ? RISP_BF16 : (tc == DType::F32 ? RISP_FP32 : RISP_FP64));  // profile slots
   ensure_workspace(f, m, tc, s);
   const int64_t ov = (int64_t)f->nocc * f->nvir;
   const int nJ = f->naux_j;
@@ -452,70 +457,83 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   need(f->ws_y, (size_t)nJ * m * dtype_size(tacc), "Y");
   if (bf) {
     need(f->ws_xbf, (size_t)m * ldt * 2, "X (BF16)");
-    need(f->ws_ybf, (size_t)nJ * m * 2, "Y (BF16)");
+    need(f->ws_ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 2, "Yt (BF16)");
   }
   const void* Tia = (f->precision == RISP_BF16 && use_f32) ? f->t_ia32.get() : f->t_ia.get();
   const void* Tij = (f->precision == RISP_BF16 && use_f32) ? f->t_ij32.get() : f->t_ij.get();
   const void* Tab = (f->precision == RISP_BF16 && use_f32) ? f->t_ab32.get() : f->t_ab.get();
 
-  // Coulomb pass 1: Y[P][m] = s_P^2 sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
-  const void* Xc = X;
-  int64_t ldx = ov;
-  if (bf) {  // BF16 copy of X with the row stride of T_ia (zero padding)
-    PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
-    store_rows_padded(X, DType::F32, ov, m, ov, f->ws_xbf.get(), DType::BF16, ldt, nullptr, 1, 1, s);
-    Xc = f->ws_xbf.get();
-    ldx = ldt;
-  }
-  const float* rs = bf ? f->scale_ia2.as<float>() : nullptr;  // s_P^2 folded into Y (exact)
   const size_t esz = dtype_size(tc);
-  {
-    PhaseScope ps(f->ctx, s, RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * m,
-                  (double)esz * ((double)nJ * ov + (double)m * ov) + 4.0 * nJ * m);
-    Gemm g;
-    g.M = nJ;
-    g.N = m;
-    g.K = (int)(bf ? ldt : ov);  // BF16: the padding columns of T_ia and X are zero
-    RISP_CHECK(ldt < (1ll << 31), RISP_E_SHAPE, "nocc*nvir too large");
-    g.tin = tc;
-    g.tout = tacc;
-    g.A = Tia;
-    g.lda = ldt;
-    g.B = Xc;
-    g.ldb = ldx;
-    g.C = f->ws_y.get();
-    g.ldc = m;
-    g.row_scale = rs;
-    g.ksplit = std::min(kMaxSplit, gemm_auto_split(g));
-    need(f->ws_split, gemm_workspace_bytes(g), "split-K");
-    gemm(g, f->ws_split.get(), s);
-  }
-  // Coulomb pass 2: sigma[m][ia] = 2 sum_P Y[P][m] T_ia[P][ia]
-  {
-    const void* Yc = f->ws_y.get();
-    if (bf) {
-      PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0, 6.0 * nJ * m);
-      convert(f->ws_y.get(), DType::F32, f->ws_ybf.get(), DType::BF16, (int64_t)nJ * m, s);
-      Yc = f->ws_ybf.get();
+  if (bf) {
+    // BF16 copy of X with the row stride of T_ia (zero padding), then the two skinny passes
+    {
+      PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
+      store_rows_padded(X, DType::F32, ov, m, ov, f->ws_xbf.get(), DType::BF16, ldt, nullptr, 1, 1, s);
     }
-    PhaseScope ps(f->ctx, s, RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * m,
-                  (double)esz * ((double)nJ * ov + (double)nJ * m) + (double)dtype_size(tv) * m * ov);
-    Gemm g;
-    g.M = m;
-    g.N = (int)ov;
-    g.K = nJ;
-    g.tin = tc;
-    g.tout = tv;
-    g.A = Yc;  // A[mm][P] = Y[P][mm]
-    g.lda = m;
-    g.a_kc = false;
-    g.B = Tia;  // B[ia][P] = T[P][ia]
-    g.ldb = ldt;
-    g.b_kc = false;
-    g.C = sig;
-    g.ldc = ov;
-    g.alpha = 2.0;
-    gemm(g, nullptr, s);
+    const int nJp = (int)pad_to(nJ, 32);
+    for (int g0 = 0; g0 < m; g0 += kCoulombMaxM) {
+      const int mg = std::min(kCoulombMaxM, m - g0);
+      {
+        // pass 1: Yt[m][P] = s_P^2 sum_ia T_ia[P][ia] X[m][ia]   (s_P^2 undoes the storage scale)
+        PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * mg,
+                      2.0 * ((double)nJ * ov + (double)mg * ov) + 4.0 * nJ * mg);
+        coulomb_y_bf16(static_cast<const uint16_t*>(Tia), nJ, ldt,
+                       static_cast<const uint16_t*>(f->ws_xbf.get()) + (size_t)g0 * ldt, mg,
+                       f->scale_ia2.as<float>(), f->ws_split.as<float>(), f->ws_split.bytes(),
+                       static_cast<uint16_t*>(f->ws_ybf.get()), nJp, s);
+      }
+      {
+        // pass 2: sigma[m][ia] = 2 sum_P Yt[m][P] T_ia[P][ia]
+        PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * mg,
+                      2.0 * (double)nJ * ov + 4.0 * (double)mg * ov);
+        coulomb_j_bf16(static_cast<const uint16_t*>(Tia), nJ, ldt, ov,
+                       static_cast<const uint16_t*>(f->ws_ybf.get()), nJp, mg, 2.0f,
+                       static_cast<float*>(sig) + (size_t)g0 * ov, s);
+      }
+    }
+  } else {
+    // Coulomb pass 1: Y[P][m] = sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
+    {
+      PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * m,
+                    (double)esz * ((double)nJ * ov + (double)m * ov) + 4.0 * nJ * m);
+      Gemm g;
+      g.M = nJ;
+      g.N = m;
+      g.K = (int)ov;
+      RISP_CHECK(ov < (1ll << 31), RISP_E_SHAPE, "nocc*nvir too large");
+      g.tin = tc;
+      g.tout = tacc;
+      g.A = Tia;
+      g.lda = ldt;
+      g.B = X;
+      g.ldb = ov;
+      g.C = f->ws_y.get();
+      g.ldc = m;
+      g.ksplit = std::min(kMaxSplit, gemm_auto_split(g));
+      need(f->ws_split, gemm_workspace_bytes(g), "split-K");
+      gemm(g, f->ws_split.get(), s);
+    }
+    // Coulomb pass 2: sigma[m][ia] = 2 sum_P Y[P][m] T_ia[P][ia]
+    {
+      PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * m,
+                    (double)esz * ((double)nJ * ov + (double)nJ * m) + (double)dtype_size(tv) * m * ov);
+      Gemm g;
+      g.M = m;
+      g.N = (int)ov;
+      g.K = nJ;
+      g.tin = tc;
+      g.tout = tv;
+      g.A = f->ws_y.get();  // A[mm][P] = Y[P][mm]
+      g.lda = m;
+      g.a_kc = false;
+      g.B = Tia;  // B[ia][P] = T[P][ia]
+      g.ldb = ldt;
+      g.b_kc = false;
+      g.C = sig;
+      g.ldc = ov;
+      g.alpha = 2.0;
+      gemm(g, nullptr, s);
+    }
   }
   // exchange inside the window
   const int nK = f->naux_k, nok = f->nok, nvk = f->nvk;
@@ -530,7 +548,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
     need(f->ws_k, (size_t)m * nok * nvk * dtype_size(tacc), "K");
     {
       // window block of X, rows and columns padded with zeros ([m][nokp][nvkp])
-      PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, 0.0,
+      PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0,
                     (double)m * nok * nvk * dtype_size(tv) + (double)m * nokp * nvkp * csz);
       gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
                     f->ws_xw.get(), tc, nokp, nvkp, s);
@@ -539,7 +557,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       const int np = std::min(pc, nK - P0);
       // product 1, one GEMM per auxiliary function P over all trial vectors at once:
       //   Mt[m][a][p][j] = s_P sum_b T_ab[P][a][b] Xw[m][j][b]   (rows a, columns (m, j))
-      std::optional<PhaseScope> ps1(std::in_place, f->ctx, s, RISP_PHASE_EXCHANGE_M,
+      std::optional<PhaseScope> ps1(std::in_place, f->ctx, s, pb + RISP_PHASE_EXCHANGE_M,
                                     2.0 * m * np * (double)nvk * nvk * nok,
                                     (double)csz * ((double)np * nvk * nvk + (double)m * nok * nvk +
                                                    (double)m * np * nvk * nok));
@@ -565,7 +583,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       ps1.reset();
       // product 2, one GEMM over the chunk: K[m][i][a] (+)= sum_(p, j) T_ij[i][P0 + p][j] Mt[m][a][p][j]
       // (rows i, columns (m, a); padding terms are zero)
-      PhaseScope ps2(f->ctx, s, RISP_PHASE_EXCHANGE_K, 2.0 * m * (double)nok * np * nok * nvk,
+      PhaseScope ps2(f->ctx, s, pb + RISP_PHASE_EXCHANGE_K, 2.0 * m * (double)nok * np * nok * nvk,
                      (double)csz * ((double)nok * np * nok + (double)m * np * nvk * nok) +
                          (double)dtype_size(tacc) * m * nok * nvk * (P0 > 0 ? 2.0 : 1.0));
       Gemm g2;
@@ -589,7 +607,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       gemm(g2, g2.ksplit > 1 ? f->ws_split.get() : nullptr, s);
     }
   }
-  PhaseScope po(f->ctx, s, RISP_PHASE_OTHER, (double)m * ov * 3.0,
+  PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, (double)m * ov * 3.0,
                 (double)m * ov * dtype_size(tv) * 3.0 + (double)m * nok * nvk * dtype_size(tacc));
   combine_sigma(sig, X, tv, f->de64.as<double>(), f->de32.as<float>(), m, f->nocc, f->nvir,
                 exch ? f->ws_k.get() : nullptr, tacc, f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk, s);

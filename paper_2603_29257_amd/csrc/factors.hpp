@@ -26,7 +26,7 @@ struct risp_ctx {
   risp::DevBuf boys;                // Boys-function Taylor table
   std::set<risp_factors*> factors;  // live factor objects (detached when the context goes away)
   bool profiling = false;
-  risp::PhaseLog phase[RISP_NPHASE];
+  risp::PhaseLog phase[RISP_NPHASE_SLOTS];
   // serving
   risp::Server* server = nullptr;
   hipStream_t serve_stream = nullptr;

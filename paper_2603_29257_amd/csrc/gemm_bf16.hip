@@ -1,15 +1,21 @@
-// BF16 products with both operands stored contraction-contiguous (C = A . B^T), the form of the
-// exchange and Coulomb products of sigma.
+// Products with both operands stored contraction-contiguous (C = A . B^T), BF16 or FP32 operands:
+// the exchange products of sigma and the plain FP32 path.
 //
-// One 256-thread block (4 wave64s, 2 x 2) computes a BM x 256 tile, BM = 64 * TI (128, 192 or
-// 256); each wave owns a (BM/2) x 128 sub-tile of TI x 4 v_mfma_f32_32x32x16_bf16 accumulators.
-// K advances in slices of 64 through two LDS stages: while the MFMAs consume one stage, the next
-// slice (already in registers) is written to the other stage and the slice after it is requested
-// from memory, so one barrier per slice suffices. LDS rows are 128 bytes with the 16-byte chunks
-// XOR-swizzled by (row / 2) mod 8, which makes both the 16-byte fragment reads of an MFMA and the
-// row-slice writes conflict-free without padding. Blocks are renumbered so that consecutive tiles
-// land on the same XCD (the dispatcher deals workgroups round-robin over the 8 XCDs), which lets
-// neighbouring tiles share operand panels in that XCD's L2.
+// One 512-thread block (8 wave64s in a 2 x 4 grid, two per SIMD) computes a BM x 256 tile,
+// BM = 64 * TI (128, 192 or 256); each wave owns a (BM/2) x 64 sub-tile of TI x 2 32x32 MFMA
+// accumulators. K advances in slices of 128 bytes per row (64 BF16 or 32 FP32 values) through two
+// LDS stages: while the MFMAs consume one stage, the next slice (already in registers) is written
+// to the other stage and the slice after it is requested from memory, so one barrier per slice
+// suffices; with two waves per SIMD, one wave's memory phase overlaps the other's MFMAs. LDS rows
+// are 128 bytes with the 16-byte chunks XOR-swizzled by (row / 2) mod 8, which makes both the
+// 16-byte fragment reads and the row-slice writes conflict-free without padding. Blocks are
+// renumbered so that consecutive tiles land on the same XCD (the dispatcher deals workgroups
+// round-robin over the 8 XCDs), which lets neighbouring tiles share operand panels in that XCD's L2.
+//
+// BF16: v_mfma_f32_32x32x16_bf16, a lane's 16-byte chunk is its 8 consecutive k. FP32:
+// v_mfma_f32_32x32x2_f32 takes one k per lane and half-wave; the contraction order is permuted
+// (step s of a chunk pair uses k = 8q + 4h + s for half-wave h), so a lane's 16-byte chunk again
+// holds the k values of four consecutive MFMAs. The sum over k does not depend on its order.
 #include "gemm.hpp"
 
 namespace risp {
@@ -17,9 +23,13 @@ namespace risp {
 namespace {
 
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
-constexpr int BN = 256, BK = 64, ROWB = 128;  // tile width, K slice, LDS bytes per row
+constexpr int BN = 256, ROWB = 128;            // tile width, LDS bytes per row (one K slice)
+constexpr int NW = 8, NT = 64 * NW;            // waves and threads per block
+constexpr int WN = BN / (NW / 2), TJ = WN / 32;  // wave tile width, MFMA tiles across it
+constexpr int RSTEP = NT / 8;                  // rows covered by one pass of the loader
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -52,10 +62,26 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int b
                                            0x00020000);
 }
 
-template <int TI, typename TO>
-__global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, int tiles_n,
-                                                         float* __restrict__ work) {
-  constexpr int BM = 64 * TI, ROWS = BM + BN, NLD = ROWS / 32, STAGE = ROWS * ROWB;
+// one 16-byte chunk of A and of B: the MFMAs of that chunk's k values
+template <typename TE> __device__ __forceinline__ f16v mfma_chunk(uint4 a, uint4 b, f16v c);
+template <> __device__ __forceinline__ f16v mfma_chunk<uint16_t>(uint4 a, uint4 b, f16v c) {
+  bf8v av, bv;
+  __builtin_memcpy(&av, &a, 16);
+  __builtin_memcpy(&bv, &b, 16);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
+}
+template <> __device__ __forceinline__ f16v mfma_chunk<float>(uint4 a, uint4 b, f16v c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  return c;
+}
+
+template <typename TE, int TI, typename TO>
+__global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tiles_n, float* __restrict__ work) {
+  constexpr int ES = sizeof(TE), BK = ROWB / ES, EPC = 16 / ES;  // element size, K slice, elements per chunk
+  constexpr int BM = 64 * TI, ROWS = BM + BN, NLD = ROWS / RSTEP, STAGE = ROWS * ROWB;
   __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
 
   // XCD-aware renumbering: hardware block w runs on XCD w % 8; logical tiles L are contiguous per XCD
@@ -67,8 +93,8 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, in
   const int tm = t % tiles_m, tn = t / tiles_m;
   const int split = zb % g.ksplit, b = zb / g.ksplit;
   const int b1 = b / g.nb2, b2 = b % g.nb2;
-  const uint16_t* A = static_cast<const uint16_t*>(g.A) + b1 * g.sa1 + b2 * g.sa2;
-  const uint16_t* B = static_cast<const uint16_t*>(g.B) + b1 * g.sb1 + b2 * g.sb2;
+  const TE* A = static_cast<const TE*>(g.A) + b1 * g.sa1 + b2 * g.sa2;
+  const TE* B = static_cast<const TE*>(g.B) + b1 * g.sb1 + b2 * g.sb2;
   const int m0 = tm * BM, n0 = tn * BN;
   int kbeg = 0, kend = g.K;
   if (g.ksplit > 1) {
@@ -78,28 +104,28 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, in
   }
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 
-  // loader: thread loads 16-byte chunk c_t of rows r_t + 32 q (q < NLD; the first BM / 32 are A
-  // rows) through buffer descriptors limited to the tile's valid rows, so rows past M or N and
+  // loader: thread loads 16-byte chunk c_t of rows r_t + RSTEP q (q < NLD; the first BM / RSTEP
+  // are A rows) through buffer descriptors limited to the tile's valid rows, so rows past M or N and
   // chunks past K (offset forced out of range) read as zero without branches
   const int tid = threadIdx.x;
   const int r_t = tid >> 3, c_t = tid & 7;
-  const int st_off = r_t * ROWB + 16 * (c_t ^ ((r_t >> 1) & 7));  // + q * 32 * ROWB
+  const int st_off = r_t * ROWB + 16 * (c_t ^ ((r_t >> 1) & 7));  // + q * RSTEP * ROWB
   const int rows_a = max(0, min(BM, g.M - m0)), rows_b = max(0, min(BN, g.N - n0));
   const __amdgpu_buffer_rsrc_t ra =
-      make_rsrc(A + (int64_t)m0 * g.lda, (int)((int64_t)rows_a * g.lda * 2));
+      make_rsrc(A + (int64_t)m0 * g.lda, (int)((int64_t)rows_a * g.lda * ES));
   const __amdgpu_buffer_rsrc_t rb =
-      make_rsrc(B + (int64_t)n0 * g.ldb, (int)((int64_t)rows_b * g.ldb * 2));
-  const uint32_t va = (uint32_t)((r_t * g.lda + 8 * c_t) * 2), vb = (uint32_t)((r_t * g.ldb + 8 * c_t) * 2);
-  const uint32_t qa = (uint32_t)(32 * g.lda * 2), qb = (uint32_t)(32 * g.ldb * 2);
+      make_rsrc(B + (int64_t)n0 * g.ldb, (int)((int64_t)rows_b * g.ldb * ES));
+  const uint32_t va = (uint32_t)((r_t * g.lda + EPC * c_t) * ES), vb = (uint32_t)((r_t * g.ldb + EPC * c_t) * ES);
+  const uint32_t qa = (uint32_t)(RSTEP * g.lda * ES), qb = (uint32_t)(RSTEP * g.ldb * ES);
 
   uint4 reg[NLD];
   auto gload = [&](int kt) {
     const int k0 = kbeg + kt * BK;
-    const bool kin = k0 + 8 * c_t < kend;
+    const bool kin = k0 + EPC * c_t < kend;
 #pragma unroll
     for (int qq = 0; qq < NLD; ++qq) {
-      const bool isA = qq < BM / 32;
-      const uint32_t off = isA ? va + qq * qa + 2 * k0 : vb + (qq - BM / 32) * qb + 2 * k0;
+      const bool isA = qq < BM / RSTEP;
+      const uint32_t off = isA ? va + qq * qa + ES * k0 : vb + (qq - BM / RSTEP) * qb + ES * k0;
       const auto v = __builtin_amdgcn_raw_buffer_load_b128(isA ? ra : rb, kin ? off : 0x80000000u, 0, 0);
       __builtin_memcpy(&reg[qq], &v, 16);
     }
@@ -107,19 +133,19 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, in
   auto sstore = [&](int stage) {
     char* base = lds + stage * STAGE + st_off;
 #pragma unroll
-    for (int qq = 0; qq < NLD; ++qq) *reinterpret_cast<uint4*>(base + qq * 32 * ROWB) = reg[qq];
+    for (int qq = 0; qq < NLD; ++qq) *reinterpret_cast<uint4*>(base + qq * RSTEP * ROWB) = reg[qq];
   };
 
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * 128;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * WN;
   const int lr = lane & 31, hi = lane >> 5, swz = (lr >> 1) & 7;
   const int a_off = (wm + lr) * ROWB, b_off = (BM + wn + lr) * ROWB;
 
-  f16v acc[TI][4];
+  f16v acc[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
@@ -132,17 +158,17 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, in
   for (int kt = 0; kt < nk; ++kt) {
     const char* buf = lds + (kt & 1) * STAGE;
 #pragma unroll
-    for (int ks = 0; ks < BK / 16; ++ks) {
+    for (int ks = 0; ks < 4; ++ks) {  // chunk pairs: half-wave h reads chunk 2 ks + h
       const int chunk = 16 * ((2 * ks + hi) ^ swz);
-      bf8v a[TI], bb[4];
+      uint4 a[TI], bb[TJ];
 #pragma unroll
-      for (int i = 0; i < TI; ++i) a[i] = *reinterpret_cast<const bf8v*>(buf + a_off + i * 32 * ROWB + chunk);
+      for (int i = 0; i < TI; ++i) a[i] = *reinterpret_cast<const uint4*>(buf + a_off + i * 32 * ROWB + chunk);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = *reinterpret_cast<const bf8v*>(buf + b_off + j * 32 * ROWB + chunk);
+      for (int j = 0; j < TJ; ++j) bb[j] = *reinterpret_cast<const uint4*>(buf + b_off + j * 32 * ROWB + chunk);
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bb[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < TJ; ++j) acc[i][j] = mfma_chunk<TE>(a[i], bb[j], acc[i][j]);
     }
     if (kt + 1 < nk) sstore((kt + 1) & 1);  // that stage was last read before the previous barrier
     if (kt + 2 < nk) gload(kt + 2);
@@ -159,7 +185,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, in
         const int row = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
         if (row >= g.M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < TJ; ++j) {
           const int col = n0 + wn + j * 32 + lr;
           if (col < g.N) Wp[(int64_t)row * g.N + col] = acc[i][j][r];
         }
@@ -169,9 +195,9 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, in
   TO* C = static_cast<TO*>(g.C) + b1 * g.sc1 + b2 * g.sc2;
   const float bs = (float)g.alpha * (g.batch_scale ? g.batch_scale[b2] : 1.f);
   const float beta = (float)g.beta;
-  int64_t coff[4];
+  int64_t coff[TJ];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < TJ; ++j) {
     const int col = n0 + wn + j * 32 + lr;
     coff[j] = col < g.N ? col_offset(g, col) : -1;
   }
@@ -184,7 +210,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_nt(Gemm g, int tiles_m, in
       const float rs = g.row_scale ? bs * g.row_scale[row] : bs;
       TO* crow = C + (int64_t)row * g.ldc;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < TJ; ++j) {
         if (coff[j] < 0) continue;
         TO* cp = crow + coff[j];
         float v = rs * acc[i][j][r];
@@ -201,24 +227,31 @@ void launch_ti(const Gemm& g, void* work, hipStream_t s) {
   const int64_t nz = (int64_t)g.nb1 * g.nb2 * g.ksplit;
   const int64_t blocks = (int64_t)tm * tn * nz;
   RISP_CHECK(blocks < (1ll << 31), RISP_E_SHAPE, "gemm grid too large");
-  if (g.tout == DType::F32)
-    k_gemm_bf16_nt<TI, float><<<(unsigned)blocks, 256, 0, s>>>(g, tm, tn, static_cast<float*>(work));
+  float* w = static_cast<float*>(work);
+  if (g.tin == DType::F32)
+    k_gemm_nt<float, TI, float><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+  else if (g.tout == DType::F32)
+    k_gemm_nt<uint16_t, TI, float><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
   else
-    k_gemm_bf16_nt<TI, uint16_t><<<(unsigned)blocks, 256, 0, s>>>(g, tm, tn, static_cast<float*>(work));
+    k_gemm_nt<uint16_t, TI, uint16_t><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
   RISP_LAUNCHED();
 }
 
 }  // namespace
 
 bool gemm_bf16_nt_eligible(const Gemm& g) {
+  const DType ma = g.mem_a == DType::Same ? g.tin : g.mem_a, mb = g.mem_b == DType::Same ? g.tin : g.mem_b;
+  const bool bf = g.tin == DType::BF16 && (g.tout == DType::F32 || g.tout == DType::BF16);
+  const bool f32 = g.tin == DType::F32 && ma == DType::F32 && mb == DType::F32 && g.tout == DType::F32;
+  if (!(bf || f32) || !g.a_kc || !g.b_kc) return false;
+  const int64_t es = bf ? 2 : 4, epc = 16 / es;  // element bytes, elements per 16-byte chunk
   const bool aligned = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0);
-  const bool strides = g.lda % 8 == 0 && g.ldb % 8 == 0 && g.sa1 % 8 == 0 && g.sa2 % 8 == 0 &&
-                       g.sb1 % 8 == 0 && g.sb2 % 8 == 0 && g.K % 8 == 0;
+  const bool strides = g.lda % epc == 0 && g.ldb % epc == 0 && g.sa1 % epc == 0 && g.sa2 % epc == 0 &&
+                       g.sb1 % epc == 0 && g.sb2 % epc == 0 && g.K % epc == 0;
   // buffer offsets within one tile (256 rows) stay below 2^31 bytes
-  const bool small = (int64_t)BN * g.lda * 2 < (1ll << 31) && (int64_t)BN * g.ldb * 2 < (1ll << 31) &&
+  const bool small = (int64_t)BN * g.lda * es < (1ll << 31) && (int64_t)BN * g.ldb * es < (1ll << 31) &&
                      g.K <= g.lda && g.K <= g.ldb;
-  return g.tin == DType::BF16 && g.a_kc && g.b_kc && aligned && strides && small &&
-         (g.tout == DType::F32 || g.tout == DType::BF16);
+  return aligned && strides && small;
 }
 
 int gemm_bf16_nt_tile(const Gemm& g) {
@@ -234,7 +267,7 @@ int gemm_bf16_nt_tile(const Gemm& g) {
     const int64_t blocks = tm * tn * nz;
     const double rows = (double)g.M / (double)(tm * bm);
     const double fill = (double)blocks / (double)(((blocks + 255) / 256) * 256);
-    const double speed = ti == 4 ? 1.0 : (ti == 3 ? 0.94 : 0.82);
+    const double speed = ti == 4 ? 1.0 : (ti == 3 ? 0.98 : 0.8);
     const double score = rows * fill * speed;
     if (score > best + 1e-9) {
       best = score;

@@ -117,7 +117,7 @@ risp_status risp_ctx_profile(risp_ctx* ctx, int32_t enable, int32_t reset, risp_
     RISP_HIP(hipStreamSynchronize(ctx->stream));
     ctx->resolve_phases();
     if (out) {
-      for (int p = 0; p < RISP_NPHASE; ++p) {
+      for (int p = 0; p < RISP_NPHASE_SLOTS; ++p) {
         out[p].launches = ctx->phase[p].launches;
         out[p].ms = ctx->phase[p].ms;
         out[p].flops = ctx->phase[p].flops;

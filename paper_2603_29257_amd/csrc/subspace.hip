@@ -25,6 +25,11 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+__device__ double wave_sum(double v) {  // full sum in every lane of the wave
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence of LDL^T pivots)
 __device__ int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
   int c = 0;
@@ -151,10 +156,11 @@ __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H
     const double K = sh_K;
     for (int r = tid; r < m; r += nt) p[r] -= K * v[r];  // q
     __syncthreads();
-    // A22 -= v q^T + q v^T
-    for (int64_t t = tid; t < (int64_t)m * m; t += nt) {
-      const int r = (int)(t / m), c = (int)(t % m);
-      H[(size_t)(j + 1 + r) * ld + j + 1 + c] -= v[r] * p[c] + p[r] * v[c];
+    // A22 -= v q^T + q v^T  (one wave per row)
+    for (int r = wave; r < m; r += nwave) {
+      double* row = H + (size_t)(j + 1 + r) * ld + j + 1;
+      const double vr = v[r], pr = p[r];
+      for (int c = lane; c < m; c += 64) row[c] -= vr * p[c] + pr * v[c];
     }
     __syncthreads();
   }
@@ -223,23 +229,28 @@ __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H
       for (int i = 0; i < n; ++i) yy[(size_t)i * k] = nrm > 0.0 ? col[i] / nrm : 0.0;
     }
     __syncthreads();
-    // Gram-Schmidt inside clusters of close eigenvalues (in ascending order)
-    for (int t = 1; t < k; ++t) {
-      for (int s = 0; s < t; ++s) {
-        if (fabs(w[t] - w[s]) >= ortol) continue;
-        double dot = 0.0;
-        for (int i = tid; i < n; i += nt) dot += Y[(size_t)i * k + s] * Y[(size_t)i * k + t];
-        dot = block_sum(dot, red);
-        for (int i = tid; i < n; i += nt) Y[(size_t)i * k + t] -= dot * Y[(size_t)i * k + s];
-        __syncthreads();
+    // Gram-Schmidt inside clusters of close eigenvalues (in ascending order), by the first wave
+    // alone: lanes over rows, wave reductions, no block barriers inside the loops
+    if (wave == 0) {
+      for (int t = 1; t < k; ++t) {
+        bool touched = false;
+        for (int s = 0; s < t; ++s) {
+          if (fabs(w[t] - w[s]) >= ortol) continue;
+          touched = true;
+          double dot = 0.0;
+          for (int i = lane; i < n; i += 64) dot += Y[(size_t)i * k + s] * Y[(size_t)i * k + t];
+          dot = wave_sum(dot);
+          for (int i = lane; i < n; i += 64) Y[(size_t)i * k + t] -= dot * Y[(size_t)i * k + s];
+        }
+        if (!touched) continue;
+        double nn = 0.0;
+        for (int i = lane; i < n; i += 64) nn += Y[(size_t)i * k + t] * Y[(size_t)i * k + t];
+        nn = wave_sum(nn);
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int i = lane; i < n; i += 64) Y[(size_t)i * k + t] *= inv;
       }
-      double nn = 0.0;
-      for (int i = tid; i < n; i += nt) nn += Y[(size_t)i * k + t] * Y[(size_t)i * k + t];
-      nn = block_sum(nn, red);
-      const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-      for (int i = tid; i < n; i += nt) Y[(size_t)i * k + t] *= inv;
-      __syncthreads();
     }
+    __syncthreads();
   }
 
   // ---- back-transformation: Z = H_0 H_1 ... H_{n-3} Y ----
@@ -256,16 +267,15 @@ __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H
       if (lane == 0) p[t] = b * acc;
     }
     __syncthreads();
-    for (int64_t q = tid; q < (int64_t)m * k; q += nt) {
-      const int c = (int)(q / k), t = (int)(q % k);
-      Y[(size_t)(j + 1 + c) * k + t] -= p[t] * v[c];
+    for (int c = wave; c < m; c += nwave) {
+      const double vc = v[c];
+      double* yr = Y + (size_t)(j + 1 + c) * k;
+      for (int t = lane; t < k; t += 64) yr[t] -= p[t] * vc;
     }
     __syncthreads();
   }
-  for (int64_t q = tid; q < (int64_t)n * k; q += nt) {
-    const int r = (int)(q / k), t = (int)(q % k);
-    Z[(size_t)r * ld + t] = Y[q];
-  }
+  for (int r = wave; r < n; r += nwave)
+    for (int t = lane; t < k; t += 64) Z[(size_t)r * ld + t] = Y[(size_t)r * k + t];
 }
 
 }  // namespace

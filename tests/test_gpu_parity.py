@@ -190,6 +190,24 @@ def test_sigma_matches_oracle(ctx, mol0, oracle0, prec, m):
     F.free()
 
 
+@pytest.mark.parametrize("m", [40, 70])
+def test_sigma_bf16_wide_blocks(ctx, mol0, oracle0, m):
+    # more than 32 vectors (two MFMA column tiles in the Coulomb kernels) and more than 64 (the
+    # Coulomb passes run in groups of 64)
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.BF16)
+    X = synth.random_trial_vectors(m, F.nocc, F.nvir, 17)
+    ref = R.sigma(oracle0, X)
+    got = ctx.sigma(F, torch.tensor(X, dtype=torch.float32, device=ctx.device)).cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _print(f"sigma bf16 m={m} max rel err {err:.3e}")
+    assert err <= 3e-2
+    # each row depends on its own trial vector only (summation splits may differ with the block size)
+    one = ctx.sigma(F, torch.tensor(X[m - 1:m], dtype=torch.float32, device=ctx.device)).cpu().numpy()
+    assert np.abs(one[0] - got[m - 1]).max() <= 1e-5 * np.abs(got[m - 1]).max()
+    F.free()
+
+
 def test_sigma_bilinear_symmetry_fp32(ctx, mol0):
     import paper_2603_29257_amd as P
     F = _gpu_factors(ctx, mol0, precision=P.FP32)
