@@ -100,7 +100,7 @@ typedef struct {
   double tol;              /* residual 2-norm convergence threshold per state */
   int32_t correction_pass; /* BF16 factors: refine the BF16-converged vectors with FP32 products */
   int32_t correction_steps;/* at most this many FP32 Davidson steps after the FP32 Rayleigh-Ritz;
-                              0 = 8 */
+                              0 = 16 */
   double bf16_tol;         /* BF16 stage stops at max(tol, bf16_tol) or when its residual stalls;
                               0 = 1e-4 */
   int32_t nx0;             /* optional initial vectors (resume): count, 0 = unit-vector guess */

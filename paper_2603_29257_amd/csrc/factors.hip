@@ -407,6 +407,11 @@ constexpr int64_t kMtBudget = 4ll << 30;      // bytes of the exchange intermedi
 // factors also run FP32 products in the correction pass).
 static int64_t pad_to(int64_t n, int64_t q) { return (n + q - 1) / q * q; }
 
+// auxiliary functions per exchange chunk for element size c: the intermediate stays within the budget
+static int64_t mt_chunk(int64_t nK, int64_t per_p, int64_t c) {
+  return std::max<int64_t>(1, std::min<int64_t>(nK, kMtBudget / (per_p * c)));
+}
+
 static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   const int csz = tc == DType::F64 ? 8 : (tc == DType::F32 ? 4 : 2);
   if (m <= f->ws_m && csz <= f->ws_csz) return;
@@ -421,10 +426,13 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
                                 coulomb_y_workspace(f->naux_j, std::min(m, kCoulombMaxM), f->ld_ia));
   if (f->naux_k > 0 && f->nok > 0 && f->nvk > 0) {
     const int64_t per_p = (int64_t)m * f->nvk * f->nokp;
-    // P-chunk: intermediate at most kMtBudget bytes and at least one auxiliary function
-    const int64_t pc = std::max<int64_t>(1, std::min<int64_t>(f->naux_k, kMtBudget / (per_p * cs)));
+    // room for the chunk of every compute type up to cs bytes per element and every block size up to
+    // m: a chunk holds at most max(one function, min(all functions, the budget))
+    int64_t mt = 0;
+    for (int64_t c = 2; c <= cs; c *= 2)
+      mt = std::max(mt, std::max(per_p * c, std::min<int64_t>(f->naux_k * per_p * c, kMtBudget)));
     f->ws_xw.alloc((size_t)m * f->nokp * f->nvkp * cs);
-    f->ws_mt.alloc((size_t)per_p * pc * cs);
+    f->ws_mt.alloc((size_t)mt);
     f->ws_k.alloc((size_t)m * f->nok * f->nvk * acc);
     split_bytes = std::max(split_bytes, (size_t)kMaxSplitK * m * f->nok * f->nvk * acc);
   }
@@ -541,9 +549,11 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   if (exch) {
     const int nokp = f->nokp, nvkp = f->nvkp;
     const size_t csz = dtype_size(tc);
+    // P-chunk from the budget rule alone (not from the workspace capacity, which depends on earlier
+    // calls), so the summation order depends only on the inputs
     const int64_t per_p = (int64_t)m * nvk * nokp;
-    const int pc = (int)std::min<int64_t>(nK, f->ws_mt.bytes() / (per_p * csz));
-    RISP_CHECK(pc >= 1, RISP_E_STATE, "sigma workspace too small for one auxiliary slice");
+    const int pc = (int)mt_chunk(nK, per_p, (int64_t)csz);
+    need(f->ws_mt, (size_t)per_p * pc * csz, "exchange intermediate");
     need(f->ws_xw, (size_t)m * nokp * nvkp * csz, "Xw");
     need(f->ws_k, (size_t)m * nok * nvk * dtype_size(tacc), "K");
     {
@@ -601,9 +611,8 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g2.n_inner = nvk;
       g2.sc_outer = (int64_t)nok * nvk;
       g2.beta = P0 > 0 ? 1.0 : 0.0;
-      const int64_t per_split = (int64_t)g2.M * g2.N * (int64_t)dtype_size(tacc);
-      g2.ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kMaxSplitK, (int64_t)gemm_auto_split(g2),
-                                                               (int64_t)f->ws_split.bytes() / per_split}));
+      g2.ksplit = std::max(1, std::min(kMaxSplitK, gemm_auto_split(g2)));
+      if (g2.ksplit > 1) need(f->ws_split, gemm_workspace_bytes(g2), "split-K (exchange)");
       gemm(g2, g2.ksplit > 1 ? f->ws_split.get() : nullptr, s);
     }
   }

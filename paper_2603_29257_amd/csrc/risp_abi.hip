@@ -382,7 +382,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       DavOptions oc = o;
       oc.x0_dev = r.X.as<double>();
       oc.nx0 = r.krows;
-      oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 8);
+      oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 16);
       SigmaFn f32 = [&](int m, const void* X, void* S) { sigma(f, m, X, S, true, s); };
       davidson(f, oc, f32, rc);
       corr_iters = rc.iters;

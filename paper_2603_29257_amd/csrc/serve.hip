@@ -116,8 +116,13 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t cap = max_space + block;
   const int64_t vsz = prm->precision == RISP_FP64 ? 8 : 4;
   const int64_t csz = std::max<int64_t>(esz, prm->precision == RISP_BF16 ? 4 : esz);
-  const int64_t sig = 1024 * nJ * block * 8 + std::min<int64_t>(1ll << 30, block * nvir * nocc * std::max<int64_t>(nK, 1) * csz) +
-                      2 * block * nocc * nvir * 8 + block * ov * 2 + 2 * nJ * block * 8;
+  // sigma workspaces (see ensure_workspace): exchange intermediate per auxiliary chunk (at most 4 GiB
+  // plus one function), window block, exchange accumulator, split-K partial sums, BF16 copies of X, Y
+  const int64_t acc = prm->precision == RISP_FP64 ? 8 : 4;
+  const int64_t blk_ov = block * nocc * nvir;
+  const int64_t mt = std::min<int64_t>(std::max<int64_t>(nK, 1) * blk_ov * csz, (4ll << 30) + blk_ov * csz);
+  const int64_t sig = mt + blk_ov * csz + blk_ov * acc + std::max(1024 * nJ * block * acc, 4 * blk_ov * acc) +
+                      block * ov * 2 + nJ * block * acc + 64 * nJ * 2;
   const int64_t dav = 2 * cap * ov * vsz + 5 * block * ov * 8 + 512 * cap * block * 8 + 4 * cap * cap * 8;
   return store + std::max(build, sig + dav) + (64ll << 20);
 }
@@ -327,7 +332,7 @@ void Server::loop() {
             oc.tol = j.opts.tol;
             oc.x0_dev = j.main_res.X.as<double>();
             oc.nx0 = j.main_res.krows;
-            oc.max_iter = 1 + (j.opts.correction_steps > 0 ? j.opts.correction_steps : 8);
+            oc.max_iter = 1 + (j.opts.correction_steps > 0 ? j.opts.correction_steps : 16);
             j.run = std::make_unique<DavidsonRun>(j.F.get(), oc, j.stream);
             j.stage = 1;
             ++it;

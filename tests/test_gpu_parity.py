@@ -208,6 +208,20 @@ def test_sigma_bf16_wide_blocks(ctx, mol0, oracle0, m):
     F.free()
 
 
+def test_sigma_repeatable_after_other_work(ctx, mol0):
+    # workspaces grow with earlier calls (the FP32 correction pass); results must not depend on that
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.BF16)
+    X = torch.tensor(synth.random_trial_vectors(10, F.nocc, F.nvir, 5), dtype=torch.float32, device=ctx.device)
+    s1 = ctx.sigma(F, X).cpu().numpy()
+    e1, _, _ = ctx.davidson(F, 5, tol=1e-5)
+    s2 = ctx.sigma(F, X).cpu().numpy()
+    e2, _, _ = ctx.davidson(F, 5, tol=1e-5)
+    assert np.array_equal(s1, s2)
+    assert np.array_equal(e1, e2)
+    F.free()
+
+
 def test_sigma_bilinear_symmetry_fp32(ctx, mol0):
     import paper_2603_29257_amd as P
     F = _gpu_factors(ctx, mol0, precision=P.FP32)
