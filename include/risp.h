@@ -89,7 +89,9 @@ typedef struct {
   int32_t precision;  /* RISP_FP64 / RISP_FP32 / RISP_BF16 */
   int32_t h_in_aux;   /* 0: hydrogen omitted from both auxiliary bases (paper's production setting) */
   int32_t bf16_scale; /* BF16 only: 1 stores each auxiliary slice scaled by a power of two */
-  int32_t reserved;
+  int32_t build_chunk_kib; /* device memory for one chunk of FP64 transformed integrals during the
+                              build, in KiB; the T_ia and T_ab builds run in as many chunks of
+                              occupied / window-virtual orbitals as needed; 0 = 16 GiB */
 } risp_params;
 
 typedef struct {

@@ -51,7 +51,7 @@ class ParamsC(C.Structure):
     _fields_ = [("c_x", C.c_double), ("beta", C.c_double), ("omega", C.c_double), ("window_ev", C.c_double),
                 ("theta", C.c_double), ("schwarz_tau", C.c_double), ("rsh_mode", C.c_int32),
                 ("window_mode", C.c_int32), ("precision", C.c_int32), ("h_in_aux", C.c_int32),
-                ("bf16_scale", C.c_int32), ("reserved", C.c_int32)]
+                ("bf16_scale", C.c_int32), ("build_chunk_kib", C.c_int32)]
 
 
 class DavOptsC(C.Structure):
@@ -163,11 +163,12 @@ class Params:
     precision: int = FP32
     h_in_aux: bool = False
     bf16_scale: bool = True
+    build_chunk_kib: int = 0
 
     def c(self):
         return ParamsC(self.c_x, self.beta, self.omega, self.window_ev, self.theta, self.schwarz_tau,
                        self.rsh_mode, self.window_mode, self.precision, int(self.h_in_aux),
-                       int(self.bf16_scale), 0)
+                       int(self.bf16_scale), int(self.build_chunk_kib))
 
 
 class System:

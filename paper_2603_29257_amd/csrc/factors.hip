@@ -105,6 +105,28 @@ static Gemm g64(int M, int N, int K) {
 struct Stored {
   DevBuf main, f32;
 };
+constexpr int64_t kBuildChunk = 16ll << 30;  // default bytes of one FP64 chunk of transformed integrals
+
+// T <- Linv T in place for T [n][cols] (row stride cols), through column panels of at most ~1 GiB
+static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t cols, DevBuf& tmp, hipStream_t s) {
+  if (n == 0 || cols == 0) return;
+  const int64_t w = std::max<int64_t>(8, std::min<int64_t>(cols, ((1ll << 30) / (8 * (int64_t)n)) / 8 * 8));
+  if (tmp.bytes() < (size_t)n * w * 8) tmp.alloc((size_t)n * w * 8);
+  for (int64_t c0 = 0; c0 < cols; c0 += w) {
+    const int nc = (int)std::min<int64_t>(w, cols - c0);
+    Gemm g = g64(n, nc, n);
+    g.A = Linv;
+    g.lda = n;
+    g.B = T + c0;  // B[j][k] = T[k][c0 + j]
+    g.ldb = cols;
+    g.b_kc = false;
+    g.C = tmp.get();
+    g.ldc = nc;
+    gemm(g, nullptr, s);
+    store_block(tmp.get(), DType::F64, nc, 0, T + c0, DType::F64, cols, 0, 1, n, nc, s);
+  }
+}
+
 static void store_factor(const double* B, int64_t rows, int64_t cols, int64_t ldd, int precision, bool keep_f32,
                          const float* scale, int64_t div, int64_t mod, Stored& out, hipStream_t s) {
   const int64_t n = std::max<int64_t>(rows * ldd, 1);
@@ -276,28 +298,50 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   gather_transpose(C.as<double>(), nmo, nao, nullptr, nocc, nvir, CvT.as<double>(), s);
 
   // ---- Coulomb factor T_ia ----
+  // Built in chunks of occupied orbitals so the FP64 intermediate stays within kBuildChunk bytes
+  // (one chunk up to a few hundred atoms): transformed integrals (Q|ia), the metric applied in place,
+  // then stored rows. BF16 factors go through their FP32 copy: the per-slice scales need the maximum
+  // over every chunk, and the BF16 rows are written from the FP32 copy at the end.
+  const bool bf = prm->precision == RISP_BF16;
+  const DType tdst = prm->precision == RISP_FP64 ? DType::F64 : DType::F32;
+  RISP_CHECK(prm->build_chunk_kib >= 0, RISP_E_ARG, "build_chunk_kib must be non-negative");
+  const int64_t chunk_bytes = prm->build_chunk_kib > 0 ? ((int64_t)prm->build_chunk_kib << 10) : kBuildChunk;
+  const size_t dsz = dtype_size(tdst);
   {
     Operator coul;  // 1/r
     DevBuf Linv;
     metric_inverse_cholesky(ctx, s, aj, coul, Linv);
+    const int nJ = aj.nfunc;
     const int64_t ov = (int64_t)nocc * nvir;
-    DevBuf Tt((size_t)aj.nfunc * ov * 8);
-    transformed_3c(ctx, s, ao, pairs, aj, coul, CoT.as<double>(), nocc, CvT.as<double>(), nvir, Tt.as<double>());
-    DevBuf B((size_t)aj.nfunc * ov * 8);
-    metric_apply(Linv.as<double>(), aj.nfunc, Tt.as<double>(), ov, B.as<double>(), s);
-    Tt.release();
     f->ld_ia = pad8(ov);
-    if (prm->precision == RISP_BF16) slice_scales(B.as<double>(), aj.nfunc, ov, prm->bf16_scale != 0, f->scale_ia, s);
-    Stored st;
-    store_factor(B.as<double>(), aj.nfunc, ov, f->ld_ia, prm->precision, f->has_f32, f->scale_ia.as<float>(), 1,
-                 aj.nfunc, st, s);
+    DevBuf& dst = bf ? f->t_ia32 : f->t_ia;
+    dst.alloc((size_t)std::max<int64_t>((int64_t)nJ * f->ld_ia, 1) * dsz);
+    fill_zero(dst.get(), dst.bytes(), s);  // zero padding columns
+    DevBuf mx((size_t)std::max(nJ, 1) * 8), tmp;
+    const int64_t ni = std::max<int64_t>(1, std::min<int64_t>(nocc, chunk_bytes / ((int64_t)nJ * std::max(nvir, 1) * 8)));
+    DevBuf Tt((size_t)nJ * ni * std::max(nvir, 1) * 8);
+    for (int i0 = 0; i0 < nocc; i0 += (int)ni) {
+      const int nic = (int)std::min<int64_t>(ni, nocc - i0);
+      const int64_t cols = (int64_t)nic * nvir;
+      transformed_3c(ctx, s, ao, pairs, aj, coul, CoT.as<double>() + (size_t)i0 * nao, nic, CvT.as<double>(), nvir,
+                     Tt.as<double>());
+      metric_apply_inplace(Linv.as<double>(), nJ, Tt.as<double>(), cols, tmp, s);
+      if (bf) row_absmax(Tt.as<double>(), nJ, cols, cols, mx.as<double>(), i0 > 0, s);
+      store_block(Tt.get(), DType::F64, cols, 0, static_cast<char*>(dst.get()) + (size_t)i0 * nvir * dsz, tdst,
+                  f->ld_ia, 0, 1, nJ, cols, s);
+    }
     RISP_HIP(hipStreamSynchronize(s));
-    f->t_ia = std::move(st.main);
-    f->t_ia32 = std::move(st.f32);
-    if (prm->precision == RISP_BF16) {
-      f->scale_ia2.alloc(aj.nfunc * sizeof(float));
-      k_mul_scales<<<ceil_div(aj.nfunc, 256), 256, 0, s>>>(f->scale_ia.as<float>(), f->scale_ia.as<float>(),
-                                                          f->scale_ia2.as<float>(), aj.nfunc);
+    Tt.release();
+    tmp.release();
+    if (bf) {
+      f->scale_ia.alloc((size_t)std::max(nJ, 1) * sizeof(float));
+      pow2_from_max(mx.as<double>(), nJ, prm->bf16_scale != 0, f->scale_ia.as<float>(), s);
+      f->t_ia.alloc((size_t)std::max<int64_t>((int64_t)nJ * f->ld_ia, 1) * 2);
+      store_rows_padded(f->t_ia32.get(), DType::F32, f->ld_ia, nJ, f->ld_ia, f->t_ia.get(), DType::BF16, f->ld_ia,
+                        f->scale_ia.as<float>(), 1, std::max(nJ, 1), s);
+      f->scale_ia2.alloc((size_t)std::max(nJ, 1) * sizeof(float));
+      k_mul_scales<<<ceil_div(std::max(nJ, 1), 256), 256, 0, s>>>(f->scale_ia.as<float>(), f->scale_ia.as<float>(),
+                                                                   f->scale_ia2.as<float>(), nJ);
       RISP_LAUNCHED();
     }
   }
@@ -329,29 +373,51 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       RISP_HIP(hipStreamSynchronize(s));
     }
     const int nK = f->naux_k;
-    DevBuf Bij((size_t)nK * nok * nok * 8), Bab((size_t)nK * nvk * nvk * 8);
-    for (size_t blk = 0; blk < blocks.size(); ++blk) {
-      DevBuf Linv;
-      metric_inverse_cholesky(ctx, s, ak, blocks[blk], Linv);
-      DevBuf Tij((size_t)nks * nok * nok * 8), Tab((size_t)nks * nvk * nvk * 8);
-      transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
-                     Tij.as<double>());
-      transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CvKT.as<double>(), nvk, CvKT.as<double>(), nvk,
-                     Tab.as<double>());
-      metric_apply(Linv.as<double>(), nks, Tij.as<double>(), (int64_t)nok * nok,
-                   Bij.as<double>() + blk * (size_t)nks * nok * nok, s);
-      metric_apply(Linv.as<double>(), nks, Tab.as<double>(), (int64_t)nvk * nvk,
-                   Bab.as<double>() + blk * (size_t)nks * nvk * nvk, s);
-      RISP_HIP(hipStreamSynchronize(s));
-    }
     // T_ij stored [i][P][j] (j padded) for the second exchange product; T_ab [P][a][b] (b padded)
     f->nokp = (int)pad8(nok);
     f->nvkp = (int)pad8(nvk);
+    // T_ab goes straight to its stored rows in chunks of window virtuals a (as T_ia above)
+    DevBuf& dab = bf ? f->t_ab32 : f->t_ab;
+    dab.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * dsz);
+    fill_zero(dab.get(), dab.bytes(), s);
+    DevBuf mxab((size_t)std::max(nK, 1) * 8), tmp;
+    const int64_t na = std::max<int64_t>(1, std::min<int64_t>(nvk, chunk_bytes / ((int64_t)nks * nvk * 8)));
+    DevBuf Bij((size_t)nK * nok * nok * 8);
+    for (size_t blk = 0; blk < blocks.size(); ++blk) {
+      DevBuf Linv;
+      metric_inverse_cholesky(ctx, s, ak, blocks[blk], Linv);
+      {
+        DevBuf Tij((size_t)nks * nok * nok * 8);
+        transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
+                       Tij.as<double>());
+        metric_apply(Linv.as<double>(), nks, Tij.as<double>(), (int64_t)nok * nok,
+                     Bij.as<double>() + blk * (size_t)nks * nok * nok, s);
+        RISP_HIP(hipStreamSynchronize(s));
+      }
+      DevBuf Tab((size_t)nks * na * nvk * 8);
+      for (int a0 = 0; a0 < nvk; a0 += (int)na) {
+        const int nac = (int)std::min<int64_t>(na, nvk - a0);
+        const int64_t cols = (int64_t)nac * nvk;
+        transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CvKT.as<double>() + (size_t)a0 * nao, nac,
+                       CvKT.as<double>(), nvk, Tab.as<double>());
+        metric_apply_inplace(Linv.as<double>(), nks, Tab.as<double>(), cols, tmp, s);
+        if (bf) row_absmax(Tab.as<double>(), nks, cols, cols, mxab.as<double>() + blk * nks, a0 > 0, s);
+        // rows (p, a) of the chunk -> stored rows (blk * nks + p) * nvk + a0 + a
+        store_block(Tab.get(), DType::F64, nvk, nac,
+                    static_cast<char*>(dab.get()) + ((size_t)blk * nks * nvk + a0) * f->nvkp * dsz, tdst, f->nvkp, nvk,
+                    nks, nac, nvk, s);
+      }
+      RISP_HIP(hipStreamSynchronize(s));
+    }
+    tmp.release();
     DevBuf sij, sab;
-    const bool bf = prm->precision == RISP_BF16;
     if (bf) {
       slice_scales(Bij.as<double>(), nK, (int64_t)nok * nok, prm->bf16_scale != 0, sij, s);
-      slice_scales(Bab.as<double>(), nK, (int64_t)nvk * nvk, prm->bf16_scale != 0, sab, s);
+      sab.alloc((size_t)std::max(nK, 1) * sizeof(float));
+      pow2_from_max(mxab.as<double>(), nK, prm->bf16_scale != 0, sab.as<float>(), s);
+      f->t_ab.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * 2);
+      store_rows_padded(f->t_ab32.get(), DType::F32, f->nvkp, (int64_t)nK * nvk, f->nvkp, f->t_ab.get(), DType::BF16,
+                        f->nvkp, sab.as<float>(), nvk, nK, s);
     }
     {
       DevBuf Bp((size_t)nK * nok * nok * 8);  // FP64 [i][P][j]
@@ -362,14 +428,6 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       RISP_HIP(hipStreamSynchronize(s));
       f->t_ij = std::move(st.main);
       f->t_ij32 = std::move(st.f32);
-    }
-    {
-      Stored st;
-      store_factor(Bab.as<double>(), (int64_t)nK * nvk, nvk, f->nvkp, prm->precision, f->has_f32, sab.as<float>(),
-                   nvk, nK, st, s);
-      RISP_HIP(hipStreamSynchronize(s));
-      f->t_ab = std::move(st.main);
-      f->t_ab32 = std::move(st.f32);
     }
     if (bf) {
       f->scale_k.alloc(nK * sizeof(float));

@@ -249,6 +249,73 @@ void row_pow2_scales(const double* A, int rows, int64_t cols, float* scale, hipS
   RISP_LAUNCHED();
 }
 
+// out[r] = max(out[r] (if acc), max_c |A[r * lda + c]|), one block per row
+__global__ __launch_bounds__(256) void k_row_absmax(const double* __restrict__ A, int64_t cols, int64_t lda,
+                                                    double* __restrict__ out, int acc) {
+  __shared__ double red[256];
+  const double* a = A + (int64_t)blockIdx.x * lda;
+  double m = 0.0;
+  for (int64_t c = threadIdx.x; c < cols; c += blockDim.x) m = fmax(m, fabs(a[c]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = acc ? fmax(out[blockIdx.x], red[0]) : red[0];
+}
+
+void row_absmax(const double* A, int rows, int64_t cols, int64_t lda, double* out, bool accumulate, hipStream_t s) {
+  if (rows == 0) return;
+  k_row_absmax<<<rows, 256, 0, s>>>(A, cols, lda, out, accumulate ? 1 : 0);
+  RISP_LAUNCHED();
+}
+
+// scale[r] = smallest power of two >= mx[r] (1 for 0 or when disabled)
+__global__ void k_pow2_from_max(const double* __restrict__ mx, int n, int enabled, float* __restrict__ scale) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double sc = 1.0;
+  if (enabled && mx[r] > 0.0) {
+    int e;
+    const double f = frexp(mx[r], &e);  // mx = f 2^e, f in [0.5, 1)
+    sc = ldexp(1.0, f == 0.5 ? e - 1 : e);
+  }
+  scale[r] = (float)sc;
+}
+
+void pow2_from_max(const double* mx, int n, bool enabled, float* scale, hipStream_t s) {
+  if (n == 0) return;
+  k_pow2_from_max<<<ceil_div(n, 256), 256, 0, s>>>(mx, n, enabled ? 1 : 0, scale);
+  RISP_LAUNCHED();
+}
+
+template <typename TS, typename TD>
+__global__ void k_store_block(const TS* __restrict__ src, int64_t lds, int64_t sps, TD* __restrict__ dst,
+                              int64_t ldd, int64_t dps, int64_t nr, int64_t nc, int64_t total) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t % nc, r = (t / nc) % nr, p = t / (nc * nr);
+    dst[(p * dps + r) * ldd + c] = cvt<TS, TD>(src[(p * sps + r) * lds + c]);
+  }
+}
+
+void store_block(const void* src, DType ts, int64_t lds, int64_t sps, void* dst, DType td, int64_t ldd, int64_t dps,
+                 int64_t np, int64_t nr, int64_t nc, hipStream_t s) {
+  const int64_t total = np * nr * nc;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 18);
+  if (ts == DType::F64 && td == DType::F64)
+    k_store_block<double, double><<<grid, 256, 0, s>>>((const double*)src, lds, sps, (double*)dst, ldd, dps, nr, nc,
+                                                       total);
+  else if (ts == DType::F64 && td == DType::F32)
+    k_store_block<double, float><<<grid, 256, 0, s>>>((const double*)src, lds, sps, (float*)dst, ldd, dps, nr, nc,
+                                                      total);
+  else
+    throw Error(RISP_E_ARG, "store_block: unsupported type pair");
+  RISP_LAUNCHED();
+}
+
 template <typename TS, typename TD>
 __global__ void k_store_padded(const TS* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
                                TD* __restrict__ dst, int64_t ldd, const float* __restrict__ scale, int64_t div,

@@ -33,6 +33,17 @@ void store_rows_padded(const void* src, DType ts, int64_t lds, int64_t rows, int
 
 inline int64_t pad8(int64_t n) { return (n + 7) / 8 * 8; }
 
+// out[r] = max_c |A[r * lda + c]| over c < cols (max with the previous out[r] when accumulate)
+void row_absmax(const double* A, int rows, int64_t cols, int64_t lda, double* out, bool accumulate, hipStream_t s);
+
+// scale[r] = smallest power of two >= mx[r] (1 where mx[r] = 0, or everywhere when not enabled)
+void pow2_from_max(const double* mx, int n, bool enabled, float* scale, hipStream_t s);
+
+// dst[(p * dps + r) * ldd + c] = (td) src[(p * sps + r) * lds + c] for p < np, r < nr, c < nc (FP64
+// source; FP64 or FP32 destination); nothing outside those positions is written
+void store_block(const void* src, DType ts, int64_t lds, int64_t sps, void* dst, DType td, int64_t ldd, int64_t dps,
+                 int64_t np, int64_t nr, int64_t nc, hipStream_t s);
+
 // T [P][i][j] -> out [i][P][j]  (element size esz bytes)
 void permute_pij_ipj(const void* T, int nP, int ni, int nj, size_t esz, void* out, hipStream_t s);
 

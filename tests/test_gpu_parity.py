@@ -174,6 +174,20 @@ def test_factors_fp32_and_bf16_storage(ctx, mol0, oracle0):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_factors_chunked_build_identical(ctx, mol0, prec):
+    # tiny build chunks (one occupied / window-virtual orbital per chunk) give the same stored factors
+    import paper_2603_29257_amd as P
+    F1 = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
+    F2 = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec], build_chunk_kib=16)
+    for name in ("t_ia", "t_ij", "t_ab") + (("scale_ia", "scale_k") if prec == "bf16" else ()):
+        a = F1.tensor(name, padded=True).double().cpu().numpy()
+        b = F2.tensor(name, padded=True).double().cpu().numpy()
+        assert np.array_equal(a, b), name
+    F1.free()
+    F2.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("m", [1, 7, 30])
 def test_sigma_matches_oracle(ctx, mol0, oracle0, prec, m):
     import paper_2603_29257_amd as P
