@@ -106,9 +106,13 @@ typedef struct {
   double bf16_tol;         /* BF16 stage stops at max(tol, bf16_tol) or when its residual stalls;
                               0 = 1e-4 */
   int32_t nx0;             /* optional initial vectors (resume): count, 0 = unit-vector guess */
-  int32_t reserved;
+  int32_t flags;           /* RISP_DAV_* bits, 0 = none */
   const float *x0;         /* [nx0][nocc*nvir] host */
 } risp_dav_opts;
+
+/* risp_dav_opts.flags: RISP_DAV_VERBOSE prints one line per iteration (stage, iteration, subspace
+ * size, largest residual over the requested states) to stderr. */
+enum { RISP_DAV_VERBOSE = 1 };
 
 typedef struct {
   int32_t iters, restarts, sigma_vectors, converged; /* main stage (BF16 stage for BF16 factors) */

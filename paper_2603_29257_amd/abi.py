@@ -57,7 +57,7 @@ class ParamsC(C.Structure):
 class DavOptsC(C.Structure):
     _fields_ = [("nstates", C.c_int32), ("block", C.c_int32), ("max_space", C.c_int32), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("correction_pass", C.c_int32), ("correction_steps", C.c_int32),
-                ("bf16_tol", C.c_double), ("nx0", C.c_int32), ("reserved", C.c_int32),
+                ("bf16_tol", C.c_double), ("nx0", C.c_int32), ("flags", C.c_int32),
                 ("x0", C.POINTER(C.c_float))]
 
 
@@ -72,6 +72,8 @@ class DavInfoC(C.Structure):
 class PhaseStatC(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
 
+
+DAV_VERBOSE = 1  # risp_dav_opts.flags: one stderr line per Davidson iteration
 
 PHASES = ("coulomb_y", "coulomb_j", "exchange_m", "exchange_k", "other")
 
@@ -446,7 +448,7 @@ class Context:
         return {k: getattr(st, k) for k, _ in ServeStatsC._fields_ if k != "reserved"}
 
     def davidson(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, correction_pass=True,
-                 x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0):
+                 x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0, verbose=False):
         ov = F.nocc * F.nvir
         e = np.zeros(nstates)
         vec = np.zeros((nstates, ov), np.float32) if want_vectors else None
@@ -454,7 +456,8 @@ class Context:
         if x0 is not None:
             x0a = np.ascontiguousarray(x0, dtype=np.float32).reshape(-1, ov)
         o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
-                     0 if x0a is None else x0a.shape[0], 0, None if x0a is None else _ptr(x0a, C.c_float))
+                     0 if x0a is None else x0a.shape[0], DAV_VERBOSE if verbose else 0,
+                     None if x0a is None else _ptr(x0a, C.c_float))
         info = DavInfoC()
         import torch
         torch.cuda.current_stream(self.device).synchronize()

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <numeric>
 
+#include <cstdio>
+
 #include "davidson.hpp"
 #include "linalg.hpp"
 #include "subspace.hpp"
@@ -448,16 +450,21 @@ void DavidsonRun::iterate(Timer& tsub) {
   double rmax = 0.0;
   for (int j = 0; j < std::min(nstates_, k); ++j) rmax = std::max(rmax, hnorm_[j]);
   res_.resid_hist.push_back(rmax);
+  if (o_.log_tag) {
+    std::fprintf(stderr, "risp davidson %s: iteration %d, subspace %d, max residual %.3e\n", o_.log_tag, it, nsub_,
+                 rmax);
+    std::fflush(stderr);
+  }
   res_.energies.assign(htheta_.begin(), htheta_.begin() + std::min(nstates_, k));
   if (k >= nstates_ && rmax < o_.tol) {
     res_.converged = true;
     finish(tsub);
     return;
   }
-  if (rmax < 0.7 * best_r_) {
+  if (rmax < 0.9 * best_r_) {
     best_r_ = rmax;
     best_it_ = it;
-  } else if (o_.stall_iters > 0 && it - best_it_ >= o_.stall_iters) {
+  } else if (o_.stall_iters > 0 && it - best_it_ >= o_.stall_iters && best_r_ <= o_.stall_below) {
     res_.stalled = true;
     finish(tsub);
     return;

@@ -26,9 +26,12 @@ struct DavOptions {
   double tol = 1e-5;
   const double* x0_dev = nullptr;  // optional initial vectors [nx0][ov] FP64 on the device
   int nx0 = 0;
-  // stop early when the largest residual has not dropped below 0.7 of its best value for this many
-  // iterations (0: never); used for the BF16 stage, whose products limit the attainable residual
+  // stop early when the largest residual has not dropped below 0.9 of its best value for this many
+  // iterations (0: never) once that best value is at most stall_below; used for the BF16 stage,
+  // whose products limit the attainable residual (slow progress far above that floor is not a stall)
   int stall_iters = 0;
+  double stall_below = 1e300;
+  const char* log_tag = nullptr;  // print one line per iteration to stderr under this tag
 };
 
 struct DavResult {

@@ -362,12 +362,14 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
     }
     SigmaFn native = [&](int m, const void* X, void* S) { sigma(f, m, X, S, false, s); };
     const bool correct = f->precision == RISP_BF16 && opts->correction_pass;
+    if (opts->flags & RISP_DAV_VERBOSE) o.log_tag = f->precision == RISP_BF16 ? "bf16" : (f->precision == RISP_FP32 ? "fp32" : "fp64");
     DavOptions ob = o;
     if (f->precision == RISP_BF16) {
       // BF16 products bound the attainable residual: stop at the stage tolerance or on a stall
       const double bt = opts->bf16_tol > 0.0 ? opts->bf16_tol : 1e-4;
       if (correct) ob.tol = std::max(o.tol, bt);
-      ob.stall_iters = 3;
+      ob.stall_iters = 4;
+      ob.stall_below = 10.0 * bt;
     }
     DavResult r;
     davidson(f, ob, native, r);
@@ -380,6 +382,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       // correction_steps FP32 Davidson steps
       auto t0 = std::chrono::steady_clock::now();
       DavOptions oc = o;
+      if (oc.log_tag) oc.log_tag = "fp32 correction";
       oc.x0_dev = r.X.as<double>();
       oc.nx0 = r.krows;
       oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 16);
