@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--cpu-sample-aux", type=int, default=48, help="exchange auxiliary slices in the CPU sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the 64-job serving stream")
     ap.add_argument("--serving-jobs", type=int, default=64)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference kernel for scaling "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -158,8 +161,42 @@ def serving_bench(jobs, tol=1e-5, max_active=8):
             "max_active": max_active, "mean_gap_s": 0.5}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "exchange_m_chainring300_traffic.json")
+
+
+def _source_digest():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2603_29257_amd", "csrc", "gemm_bf16.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the exchange kernel from the committed counter runs, or None when the
+    kernel source changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("kernel_source_sha256_16") != _source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_calibration(mib):
+    import torch
+    n = (mib << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 5}))
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding over the auxiliary "
                                    "index is a design note, not an implemented path", "n_gpus": args.gpus}))
@@ -224,7 +261,7 @@ def main():
     achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": "exchange M^P = T_ab^P X (BF16 MFMA, FP32 accumulate)",
                 "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"],
-                "traffic": None, "launches": ph["launches"], "avg_launch_ms": per_launch_ms,
+                "traffic": recorded_traffic(), "launches": ph["launches"], "avg_launch_ms": per_launch_ms,
                 "flops_per_launch": per_launch_flops}
     def phase_table(pr):
         return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
