@@ -155,6 +155,14 @@ __global__ void k_sym_update(double* H, int ld, const double* Hn, int nall, int 
   }
 }
 
+// H[i][j] = (i == j) ? theta[i] : 0 for i, j < n
+__global__ void k_diag_H(double* H, int ld, int n, const double* theta) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  H[(int64_t)i * ld + j] = i == j ? theta[i] : 0.0;
+}
+
 __global__ void k_copy_sub(const double* H, int ld, int n, double* out, int ldo) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * n) return;
@@ -198,13 +206,12 @@ DavidsonRun::DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s) : 
   H_.alloc((size_t)ld_ * ld_ * 8);
   Hw_.alloc((size_t)ld_ * ld_ * 8);
   Zs_.alloc((size_t)ld_ * ld_ * 8);
-  eigws_.alloc(subspace_eig_workspace(cap_, block_));
+  eigws_.alloc(subspace_eig_workspace(cap_, std::min(2 * block_, cap_)));
   theta_.alloc((size_t)ld_ * 8);
   res_.X.alloc((size_t)block_ * ov * 8);
   AX_.alloc((size_t)block_ * ov * 8);
   T_.alloc((size_t)block_ * ov * 8);
   T2_.alloc((size_t)block_ * ov * 8);
-  Tsave_.alloc((size_t)block_ * ov * 8);
   Cmix_.alloc((size_t)cap_ * block_ * 8);
   G_.alloc((size_t)block_ * block_ * 8);
   Cf_.alloc((size_t)block_ * block_ * 8);
@@ -396,14 +403,6 @@ void DavidsonRun::complete() {
   } else if (state_ == State::Append) {
     update_H(nsub_ + rq_.n, nsub_, rq_.n);
     nsub_ += rq_.n;
-  } else if (state_ == State::Restart) {
-    nsub_ = rq_.n;
-    update_H(nsub_, 0, nsub_);
-    ++res_.restarts;
-    // the corrections saved before the restart go into the fresh subspace
-    RISP_HIP(hipMemcpyAsync(T_.get(), Tsave_.get(), (size_t)nt_saved_ * ov * 8, hipMemcpyDeviceToDevice, s_));
-    append_corrections(nt_saved_, tsub);
-    return;
   }
   iterate(tsub);
 }
@@ -437,7 +436,8 @@ void DavidsonRun::iterate(Timer& tsub) {
   k_copy_sub<<<ceil_div((int64_t)nsub_ * nsub_, 256), 256, 0, s_>>>(H_.as<double>(), ld_, nsub_, Hw_.as<double>(), ld_);
   RISP_LAUNCHED();
   const int k = std::min(block_, nsub_);
-  subspace_eig(Hw_.as<double>(), nsub_, ld_, k, theta_.as<double>(), Zs_.as<double>(), eigws_.as<double>(), s_);
+  const int kk = std::min(2 * block_, nsub_);  // Ritz pairs kept by a thick restart
+  subspace_eig(Hw_.as<double>(), nsub_, ld_, kk, theta_.as<double>(), Zs_.as<double>(), eigws_.as<double>(), s_);
   combine_rows(Zs_.as<double>(), ld_, nsub_, k, V_.get(), X, 1.0, 0.0);
   combine_rows(Zs_.as<double>(), ld_, nsub_, k, W_.get(), AX_.as<double>(), 1.0, 0.0);
   k_residual<<<grid_for((int64_t)k * ov), 256, 0, s_>>>(AX_.as<double>(), X, theta_.as<double>(), k, ov);
@@ -486,20 +486,46 @@ void DavidsonRun::iterate(Timer& tsub) {
   k_scale_rows<<<grid_for((int64_t)nt * ov), 256, 0, s_>>>(T_.as<double>(), nt, ov, norms_.as<double>());
   RISP_LAUNCHED();
   if (nsub_ + nt > max_space_) {
-    // restart: the current Ritz vectors become the subspace; their products are recomputed
-    RISP_HIP(hipMemcpyAsync(Tsave_.get(), T_.get(), (size_t)nt * ov * 8, hipMemcpyDeviceToDevice, s_));
-    RISP_HIP(hipMemcpyAsync(T_.get(), X, (size_t)k * ov * 8, hipMemcpyDeviceToDevice, s_));
-    const int nk = orth_block(k);
-    RISP_CHECK(nk > 0, RISP_E_STATE, "restart lost every Ritz vector");
-    store_T(0, nk);
-    RISP_HIP(hipStreamSynchronize(s_));
-    res_.t_subspace += tsub.sec();
-    nt_saved_ = nt;
-    rq_ = {0, nk};
-    state_ = State::Restart;
-    return;
+    // thick restart: the lowest `keep` Ritz vectors become the subspace; their products are the same
+    // combination of W (no sigma), and the projected matrix is diag(theta)
+    const int keep = std::max(1, std::min({kk, cap_ - nt, nsub_}));
+    thick_restart(keep);
+    ++res_.restarts;
   }
   append_corrections(nt, tsub);
+}
+
+// V[0:keep] <- V Z[:, 0:keep], W[0:keep] <- W Z[:, 0:keep] (FP64 products, stored in the vector type),
+// H <- diag(theta[0:keep])
+void DavidsonRun::thick_restart(int keep) {
+  const int64_t ov = ov_;
+  const size_t bytes = (size_t)keep * ov * vsz_;
+  if (Rv_.bytes() < bytes) Rv_.alloc(bytes);
+  if (Rw_.bytes() < bytes) Rw_.alloc(bytes);
+  for (int w = 0; w < 2; ++w) {
+    Gemm g;  // out[i][ia] = sum_s Z[s][i] src[s][ia]
+    g.M = keep;
+    g.N = (int)ov;
+    g.K = nsub_;
+    g.tin = DType::F64;
+    g.tout = tvec_;
+    g.mem_a = DType::F64;
+    g.mem_b = tvec_;
+    g.A = Zs_.get();
+    g.lda = ld_;
+    g.a_kc = false;
+    g.B = w == 0 ? V_.get() : W_.get();
+    g.ldb = ov;
+    g.b_kc = false;
+    g.C = w == 0 ? Rv_.get() : Rw_.get();
+    g.ldc = ov;
+    gemm(g, nullptr, s_);
+  }
+  RISP_HIP(hipMemcpyAsync(V_.get(), Rv_.get(), bytes, hipMemcpyDeviceToDevice, s_));
+  RISP_HIP(hipMemcpyAsync(W_.get(), Rw_.get(), bytes, hipMemcpyDeviceToDevice, s_));
+  k_diag_H<<<ceil_div((int64_t)keep * keep, 256), 256, 0, s_>>>(H_.as<double>(), ld_, keep, theta_.as<double>());
+  RISP_LAUNCHED();
+  nsub_ = keep;
 }
 
 void davidson(risp_factors* f, const DavOptions& o, const SigmaFn& sigma_fn, DavResult& res) {

@@ -62,7 +62,7 @@ class DavidsonRun {
   DavResult& result() { return res_; }
 
  private:
-  enum class State { Init, Append, Restart, Done };
+  enum class State { Init, Append, Done };
   void* vrow(DevBuf& b, int r);
   void update_H(int nall, int n0, int nn);
   void row_norms(const double* R, int k, double* out_dev);
@@ -74,6 +74,7 @@ class DavidsonRun {
   void iterate(Timer& tsub);
   void append_corrections(int nt, Timer& tsub);
   void finish(Timer& tsub);
+  void thick_restart(int keep);
 
   risp_factors* f_;
   DavOptions o_;
@@ -83,14 +84,14 @@ class DavidsonRun {
   DType tvec_ = DType::F32;
   size_t vsz_ = 4;
   int nstates_ = 0, block_ = 0, max_space_ = 0, cap_ = 0, ld_ = 0, max_iter_ = 0, nblk_ = 1;
-  int nsub_ = 0, nt_saved_ = 0, best_it_ = 0;
+  int nsub_ = 0, best_it_ = 0;
   double best_r_ = 1e300;
   State state_ = State::Init;
   Request rq_;
   DavResult res_;
   std::vector<double> hnorm_, htheta_;
-  DevBuf V_, W_, H_, Hw_, Zs_, eigws_, theta_, AX_, T_, T2_, Tsave_, Cmix_, G_, Cf_, partial_, norms_, kept_,
-      src_, Hn_, split_;
+  DevBuf V_, W_, H_, Hw_, Zs_, eigws_, theta_, AX_, T_, T2_, Cmix_, G_, Cf_, partial_, norms_, kept_,
+      src_, Hn_, split_, Rv_, Rw_;
 };
 
 void davidson(risp_factors* f, const DavOptions& o, const SigmaFn& sigma_fn, DavResult& res);

@@ -57,8 +57,12 @@ struct Job {
   risp_dav_info info{};
   double t_submit = 0, t_admit = -1, t_first_sigma = -1, t_done = -1;
 
+  // every device allocation of the job is released here, on the scheduler thread: a Job object that
+  // still held device memory when risp_poll destroys it would call hipFree from the polling thread
+  // while the scheduler thread may be capturing a graph on its streams
   void release_device() {
     run.reset();
+    main_res = DavResult();
     F.reset();
     if (stream) {
       (void)hipStreamSynchronize(stream);
@@ -123,7 +127,8 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t mt = std::min<int64_t>(std::max<int64_t>(nK, 1) * blk_ov * csz, (4ll << 30) + blk_ov * csz);
   const int64_t sig = mt + blk_ov * csz + blk_ov * acc + std::max(1024 * nJ * block * acc, 4 * blk_ov * acc) +
                       block * ov * 2 + nJ * block * acc + 64 * nJ * 2;
-  const int64_t dav = 2 * cap * ov * vsz + 5 * block * ov * 8 + 512 * cap * block * 8 + 4 * cap * cap * 8;
+  const int64_t dav = 2 * cap * ov * vsz + 4 * block * ov * 8 + 4 * block * ov * vsz + 512 * cap * block * 8 +
+                      4 * cap * cap * 8;
   return store + std::max(build, sig + dav) + (64ll << 20);
 }
 
