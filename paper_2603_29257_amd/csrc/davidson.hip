@@ -436,7 +436,8 @@ void DavidsonRun::iterate(Timer& tsub) {
   k_copy_sub<<<ceil_div((int64_t)nsub_ * nsub_, 256), 256, 0, s_>>>(H_.as<double>(), ld_, nsub_, Hw_.as<double>(), ld_);
   RISP_LAUNCHED();
   const int k = std::min(block_, nsub_);
-  const int kk = std::min(2 * block_, nsub_);  // Ritz pairs kept by a thick restart
+  // Ritz pairs kept by a thick restart; computed only when this iteration may restart
+  const int kk = nsub_ + block_ > max_space_ ? std::min(2 * block_, nsub_) : k;
   subspace_eig(Hw_.as<double>(), nsub_, ld_, kk, theta_.as<double>(), Zs_.as<double>(), eigws_.as<double>(), s_);
   combine_rows(Zs_.as<double>(), ld_, nsub_, k, V_.get(), X, 1.0, 0.0);
   combine_rows(Zs_.as<double>(), ld_, nsub_, k, W_.get(), AX_.as<double>(), 1.0, 0.0);
