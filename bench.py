@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--nstates", type=int, default=15)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison steps")
+    ap.add_argument("--no-bf16", action="store_true", help="time only the plain FP32 path (long workloads)")
+    ap.add_argument("--verbose", action="store_true", help="one stderr line per Davidson iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-aux", type=int, default=48, help="exchange auxiliary slices in the CPU sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the 64-job serving stream (the default)")
@@ -221,14 +223,17 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = ctx.build_factors(sysc, P.Params(precision=P.PRECISIONS[prec]))
-        e, _, info = ctx.davidson(F, args.nstates, tol=args.tol, want_vectors=False, allow_notconv=True)
+        e, _, info = ctx.davidson(F, args.nstates, tol=args.tol, want_vectors=False, allow_notconv=True,
+                                  verbose=args.verbose)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         desc = F.desc
         F.free()
         return dt, e, info, desc
 
-    precs = ["bf16"] + ([] if args.no_fp32 else ["fp32"])
+    precs = ([] if args.no_bf16 else ["bf16"]) + ([] if args.no_fp32 else ["fp32"])
+    if not precs:
+        sys.exit("nothing to time: --no-bf16 and --no-fp32 together")
     for prec in precs:
         for _ in range(args.warmup):
             step(prec)
@@ -256,41 +261,44 @@ def main():
                          t_build=info.t_build, t_sigma=info.t_sigma, t_subspace=info.t_subspace,
                          t_correct=info.t_correct, desc=desc)
 
-    b = res["bf16"]
-    # dominant kernel of the BF16 sigma blocks: the exchange product M = T_ab X (one launch per chunk)
-    ph = b["prof"]["bf16"]["exchange_m"]
+    mp_ = "bf16" if "bf16" in res else "fp32"  # the path the value and the roofline describe
+    b = res[mp_]
+    # dominant kernel of the sigma blocks: the exchange product M = T_ab X (one launch per chunk)
+    ph = b["prof"][mp_]["exchange_m"]
     per_launch_ms = ph["ms"] / max(ph["launches"], 1)
     per_launch_flops = ph["flops"] / max(ph["launches"], 1)
     achieved = per_launch_flops / (per_launch_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "exchange M^P = T_ab^P X (BF16 MFMA, FP32 accumulate)",
-                "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"],
-                "traffic": recorded_traffic(), "launches": ph["launches"], "avg_launch_ms": per_launch_ms,
-                "flops_per_launch": per_launch_flops}
+    roofline = {"bound": "mfma",
+                "kernel": ("exchange M^P = T_ab^P X (BF16 MFMA, FP32 accumulate)" if mp_ == "bf16"
+                           else "exchange M^P = T_ab^P X (FP32 MFMA)"),
+                "achieved": achieved, "peak": PEAK[mp_], "unit": "TFLOP/s", "frac": achieved / PEAK[mp_],
+                "traffic": recorded_traffic() if (mp_ == "bf16" and args.workload == "chainring300") else None,
+                "launches": ph["launches"], "avg_launch_ms": per_launch_ms, "flops_per_launch": per_launch_flops}
     def phase_table(pr):
         return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                     "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0,
                     "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
                 for k, v in pr.items() if v["launches"] > 0}
-    phases = phase_table(b["prof"]["bf16"])
-    phases_corr = phase_table(b["prof"]["fp32"])
+    phases = phase_table(b["prof"][mp_])
+    phases_corr = phase_table(b["prof"]["fp32"]) if mp_ == "bf16" else {}
     d = b["desc"]
     out = {
         "metric": "time-to-15-states & sigma-build TFLOP/s, BF16 vs plain FP32; p50/p99 latency",
         "value": b["sigma_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": b["t2s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16", "data": "synthetic",
+        "dtype": mp_, "data": "synthetic",
         "config": {"workload": args.workload, "atoms": int(mol.natm), "nao": d.nao, "nocc": d.nocc, "nvir": d.nvir,
                    "naux_j": d.naux_j, "naux_k": d.naux_k, "nocc_k": d.nocc_k, "nvir_k": d.nvir_k,
                    "npair": d.npair, "nstates": args.nstates, "block": 30, "tol": args.tol, "window_ev": 40.0,
                    "c_x": 0.22, "beta": 0.78, "omega": 0.2},
         "time_to_15_states_s": {p: res[p]["t2s"] for p in res},
         "sigma_tflops": {p: res[p]["sigma_tflops"] for p in res},
-        "sigma_tflops_fp32_correction_stage": res["bf16"]["sigma_tflops_correction"],
+        "sigma_tflops_fp32_correction_stage": res["bf16"]["sigma_tflops_correction"] if "bf16" in res else None,
         "converged": {p: res[p]["converged"] for p in res},
         "iterations": {p: res[p]["iters"] for p in res},
         "breakdown_s": {p: {"build": res[p]["t_build"], "sigma": res[p]["t_sigma"], "subspace": res[p]["t_subspace"],
                             "correction": res[p]["t_correct"]} for p in res},
-        "phases_bf16": phases,
+        f"phases_{mp_}": phases,
         "phases_bf16_job_fp32_correction": phases_corr,
         "roofline": roofline,
         "latency": None if jobs is None else serving_bench(jobs, tol=args.tol),

@@ -111,7 +111,10 @@ constexpr int64_t kBuildChunk = 16ll << 30;  // default bytes of one FP64 chunk 
 static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t cols, DevBuf& tmp, hipStream_t s) {
   if (n == 0 || cols == 0) return;
   const int64_t w = std::max<int64_t>(8, std::min<int64_t>(cols, ((1ll << 30) / (8 * (int64_t)n)) / 8 * 8));
-  if (tmp.bytes() < (size_t)n * w * 8) tmp.alloc((size_t)n * w * 8);
+  if (tmp.bytes() < (size_t)n * w * 8) {
+    RISP_HIP(hipStreamSynchronize(s));  // earlier panels may still read the old buffer
+    tmp.alloc((size_t)n * w * 8);
+  }
   for (int64_t c0 = 0; c0 < cols; c0 += w) {
     const int nc = (int)std::min<int64_t>(w, cols - c0);
     Gemm g = g64(n, nc, n);
@@ -344,6 +347,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
                                                                    f->scale_ia2.as<float>(), nJ);
       RISP_LAUNCHED();
     }
+    RISP_HIP(hipStreamSynchronize(s));  // mx and Linv die at the end of this scope
   }
 
   // ---- exchange factors T_ij, T_ab in the J^ metric ----
