@@ -48,6 +48,16 @@ enum {
 
 /* precision of the stored factors and of the sigma contractions */
 enum { RISP_FP64 = 0, RISP_FP32 = 1, RISP_BF16 = 2 };
+
+/* Coulomb route (section on on-the-fly Coulomb evaluation). RISP_J_MO stores T_ia and forms
+ * 2 T_ia (T_jb^T X) in two streaming passes. RISP_J_AO_DIRECT stores no T_ia: per sigma block it
+ * forms the AO transition densities D_m = C_occ X_m C_vir^T, contracts them with (mu nu|Q)
+ * regenerated over the screened pairs, applies the inverse metric, contracts back with (mu nu|P)
+ * regenerated again and transforms J_m = C_occ^T U_m C_vir, all in FP64; for molecules whose T_ia
+ * does not fit in device memory. The AO transition densities are dense FP64 [nao][nao] slices, so
+ * the route takes nao <= 16384. Served jobs take RISP_J_MO only (the route synchronises inside
+ * sigma and cannot run in the serving loop's graphs). */
+enum { RISP_J_MO = 0, RISP_J_AO_DIRECT = 1 };
 /* reading of the range-separated exchange: one RI in the J^ metric (paper eq. K_mia_RSH) or
  * alpha RI(1/r) + beta RI(erf) stacked along the auxiliary index */
 enum { RISP_RSH_COMBINED = 0, RISP_RSH_SPLIT = 1 };
@@ -92,6 +102,8 @@ typedef struct {
   int32_t build_chunk_kib; /* device memory for one chunk of FP64 transformed integrals during the
                               build, in KiB; the T_ia and T_ab builds run in as many chunks of
                               occupied / window-virtual orbitals as needed; 0 = 16 GiB */
+  int32_t j_mode;     /* RISP_J_*: how the Coulomb term of sigma is formed */
+  int32_t reserved;   /* 0 */
 } risp_params;
 
 typedef struct {
@@ -143,7 +155,8 @@ typedef struct {
   const float *scale_k;   /* dev [naux_k] product of the T_ij and T_ab scales (BF16), else NULL */
   const int32_t *occ_k;   /* dev [nocc_k] window occupied indices, ascending */
   const int32_t *vir_k;   /* dev [nvir_k] window virtual indices (0-based in the virtual space) */
-  int64_t ld_ia;          /* row stride of t_ia: nocc*nvir rounded up to a multiple of 8 */
+  int64_t ld_ia;          /* row stride of t_ia: nocc*nvir rounded up to a multiple of 8 (t_ia is
+                             NULL for factors built with RISP_J_AO_DIRECT) */
   int32_t ld_ij, ld_ab;   /* row strides of t_ij and t_ab: nocc_k, nvir_k rounded up likewise */
 } risp_factors_desc;
 

@@ -238,19 +238,23 @@ def dense_A(F: Factors) -> np.ndarray:
     return A
 
 
-def sigma(F: Factors, X: np.ndarray) -> np.ndarray:
+def sigma(F: Factors, X: np.ndarray, coulomb=None) -> np.ndarray:
     """sigma = A X for a block X [m][nocc][nvir], matrix-free.
 
     sigma = de*X + 2 sum_P B^P_ia (sum_jb B^P_jb X_mjb) - scatter_window(K), where the exchange part
-    K_mia = sum_P sum_jb Bx^P_ij Bx^P_ab X_mjb runs over the window only.
+    K_mia = sum_P sum_jb Bx^P_ij Bx^P_ab X_mjb runs over the window only. `coulomb`: the Coulomb
+    term 2 J [m][nocc][nvir] computed elsewhere (coulomb_ao) in place of the one from B_ia.
     """
     X = np.asarray(X, dtype=np.float64)
     m = X.shape[0]
     o, v = F.nocc, F.nvir
     out = F.de[None] * X
-    Bf = F.B_ia.reshape(F.B_ia.shape[0], o * v)
-    Y = Bf @ X.reshape(m, o * v).T  # [P, m]
-    out += 2.0 * (Y.T @ Bf).reshape(m, o, v)
+    if coulomb is None:
+        Bf = F.B_ia.reshape(F.B_ia.shape[0], o * v)
+        Y = Bf @ X.reshape(m, o * v).T  # [P, m]
+        out += 2.0 * (Y.T @ Bf).reshape(m, o, v)
+    else:
+        out += coulomb
     if F.Bx_ij.shape[0]:
         Xw = np.ascontiguousarray(X[:, F.occK][:, :, F.virK])  # [m, noK, nvK] (contiguous for BLAS)
         K = np.zeros_like(Xw)
@@ -259,6 +263,36 @@ def sigma(F: Factors, X: np.ndarray) -> np.ndarray:
             K += F.Bx_ij[P] @ M  # K_mia += sum_j Bx^P_ij M^P_mja (matmul broadcast over m)
         out[np.ix_(np.arange(m), F.occK, F.virK)] -= K
     return out
+
+
+def coulomb_ao(mol, X: np.ndarray, prm: Params = Params(), pair_mask=None) -> np.ndarray:
+    """2 J_mia by the AO-density route (section on on-the-fly Coulomb evaluation), no stored T_ia.
+
+    D_m = C_occ X_m C_vir^T (AO transition density); R_Q = sum_(mu nu) (mu nu|Q) D_m,mu nu;
+    R~ solves (P|Q) R~ = R; U_m = sum_P (mu nu|P) R~_P; J_m = C_occ^T U_m C_vir. The same Schwarz pair
+    mask as build_factors (by default), so J equals the stored-factor route up to rounding.
+    Returns [m][nocc][nvir].
+    """
+    coords, shells = mol.coords, mol.shells
+    auxJ, _ = select_aux(mol.Z, mol.aux_radius, prm.theta, prm.h_in_aux)
+    if pair_mask is None:
+        _, pair_mask, _ = schwarz_pairs(coords, shells, auxJ, prm.schwarz_tau)
+    C = mol.mo_coeff
+    nocc = mol.nocc
+    Co, Cv = C[:, :nocc], C[:, nocc:]
+    X = np.asarray(X, dtype=np.float64)
+    D = np.einsum("mi,kia,na->kmn", Co, X, Cv, optimize=True)
+    V3 = I.int3c(coords, shells, auxJ, None, pair_mask)  # [mu][nu][P]
+    R = np.einsum("mnP,kmn->Pk", V3, D, optimize=True)
+    Rt = sla.cho_solve(sla.cho_factor(I.int2c(coords, auxJ), lower=True), R)
+    U = np.einsum("mnP,Pk->kmn", V3, Rt, optimize=True)
+    return 2.0 * np.einsum("mi,kmn,na->kia", Co, U, Cv, optimize=True)
+
+
+def sigma_ao(F: Factors, mol, X: np.ndarray, prm: Params = Params()) -> np.ndarray:
+    """sigma = A X with the Coulomb term from coulomb_ao (F supplies the gaps and exchange factors)."""
+    X = np.asarray(X, dtype=np.float64)
+    return sigma(F, X, coulomb=coulomb_ao(mol, X, prm))
 
 
 def lowest_eigh(A, n):

@@ -21,6 +21,7 @@ RISP_E_ARG, RISP_E_SHAPE, RISP_E_NOMEM, RISP_E_HIP, RISP_E_NOTCONV, RISP_E_STATE
     -1, -2, -3, -4, -5, -6, -7)
 FP64, FP32, BF16 = 0, 1, 2
 RSH_COMBINED, RSH_SPLIT = 0, 1
+J_MO, J_AO_DIRECT = 0, 1
 WIN_ABSOLUTE, WIN_FRONTIER = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
@@ -51,7 +52,8 @@ class ParamsC(C.Structure):
     _fields_ = [("c_x", C.c_double), ("beta", C.c_double), ("omega", C.c_double), ("window_ev", C.c_double),
                 ("theta", C.c_double), ("schwarz_tau", C.c_double), ("rsh_mode", C.c_int32),
                 ("window_mode", C.c_int32), ("precision", C.c_int32), ("h_in_aux", C.c_int32),
-                ("bf16_scale", C.c_int32), ("build_chunk_kib", C.c_int32)]
+                ("bf16_scale", C.c_int32), ("build_chunk_kib", C.c_int32), ("j_mode", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class DavOptsC(C.Structure):
@@ -166,11 +168,12 @@ class Params:
     h_in_aux: bool = False
     bf16_scale: bool = True
     build_chunk_kib: int = 0
+    j_mode: int = 0  # J_MO or J_AO_DIRECT
 
     def c(self):
         return ParamsC(self.c_x, self.beta, self.omega, self.window_ev, self.theta, self.schwarz_tau,
                        self.rsh_mode, self.window_mode, self.precision, int(self.h_in_aux),
-                       int(self.bf16_scale), int(self.build_chunk_kib))
+                       int(self.bf16_scale), int(self.build_chunk_kib), int(self.j_mode), 0)
 
 
 class System:
@@ -260,6 +263,8 @@ class Factors:
                   "vir_k": ((d.nvir_k,), torch.int32)}
         shape, dtype = shapes[which]
         ptr = getattr(d, which)
+        if which == "t_ia" and not ptr and d.naux_j > 0:
+            raise ValueError("t_ia is not stored by factors built with the AO Coulomb route")
         out = torch.zeros(shape, dtype=dtype, device=self.ctx.device)
         if ptr and out.numel():
             nbytes = out.numel() * out.element_size()

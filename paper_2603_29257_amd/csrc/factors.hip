@@ -8,12 +8,19 @@
 #include "factors.hpp"
 #include "linalg.hpp"
 
+static size_t shell_bytes(const risp::DevShells& d) {
+  return d.x.bytes() + d.y.bytes() + d.z.bytes() + d.ex.bytes() + d.cn.bytes() + d.l.bytes() + d.off.bytes() +
+         d.atom.bytes();
+}
+
 int64_t risp_factors::bytes() const {
   return (int64_t)(t_ia.bytes() + t_ij.bytes() + t_ab.bytes() + t_ia32.bytes() + t_ij32.bytes() +
                    t_ab32.bytes() + scale_ia.bytes() + scale_ia2.bytes() + scale_k.bytes() + occ_k.bytes() +
                    vir_k.bytes() + pos_o.bytes() + pos_v.bytes() + de64.bytes() + de32.bytes() +
                    ws_y.bytes() + ws_ybf.bytes() + ws_xbf.bytes() + ws_xw.bytes() + ws_mt.bytes() +
-                   ws_k.bytes() + ws_split.bytes());
+                   ws_k.bytes() + ws_split.bytes() + shell_bytes(ao_sh) + shell_bytes(auxj_sh) + pairs.a.bytes() +
+                   pairs.b.bytes() + linv_j.bytes() + co_t.bytes() + cv_t.bytes() + ws_ao_t.bytes() +
+                   ws_ao_d.bytes() + ws_ao_v.bytes() + ws_ao_r.bytes());
 }
 
 void risp_ctx::resolve_phases() {
@@ -254,6 +261,9 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   RISP_CHECK(prm->theta > 0.0 && prm->schwarz_tau >= 0.0 && prm->omega >= 0.0, RISP_E_ARG,
              "theta must be positive, tau and omega non-negative");
   RISP_CHECK(prm->beta == 0.0 || prm->omega > 0.0, RISP_E_ARG, "beta != 0 needs omega > 0");
+  RISP_CHECK(prm->j_mode == RISP_J_MO || prm->j_mode == RISP_J_AO_DIRECT, RISP_E_ARG, "bad j_mode");
+  RISP_CHECK(prm->j_mode == RISP_J_MO || sys->nao <= kAoMaxNao, RISP_E_SHAPE,
+             "the AO Coulomb route takes nao <= " + std::to_string(kAoMaxNao));
   hipStream_t s = stream ? stream : ctx->stream;
   const int nao = sys->nao, nmo = sys->nmo, nocc = sys->nocc, nvir = nmo - nocc;
   f->ctx = ctx;
@@ -264,6 +274,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   f->nvir = nvir;
   f->precision = prm->precision;
   f->has_f32 = prm->precision == RISP_BF16;
+  f->j_mode = prm->j_mode;
 
   // auxiliary bases (section on exchange-space truncation: H omitted, J = s + p, K = s)
   std::vector<risp_shell> auxJ, auxK;
@@ -310,7 +321,35 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   RISP_CHECK(prm->build_chunk_kib >= 0, RISP_E_ARG, "build_chunk_kib must be non-negative");
   const int64_t chunk_bytes = prm->build_chunk_kib > 0 ? ((int64_t)prm->build_chunk_kib << 10) : kBuildChunk;
   const size_t dsz = dtype_size(tdst);
-  {
+  if (f->j_mode == RISP_J_AO_DIRECT) {
+    // no stored T_ia: keep the metric factor and plan the auxiliary chunks of the per-sigma integral
+    // passes (dense (mu nu|P) slices of at most ~2 GiB, whole shells)
+    Operator coul;
+    metric_inverse_cholesky(ctx, s, aj, coul, f->linv_j);
+    f->j_op = coul;
+    f->ld_ia = pad8((int64_t)nocc * nvir);
+    const int64_t per_func = (int64_t)nao * nao * 8;
+    const int max_f = (int)std::max<int64_t>(3, std::min<int64_t>(256, (2ll << 30) / per_func));
+    const int ns = (int)auxJ.size();
+    f->ao_s0.clear();
+    f->ao_f0.clear();
+    f->ao_max_f = 0;
+    int fo = 0;
+    for (int s0 = 0; s0 < ns;) {
+      int s1 = s0, nf = 0;
+      while (s1 < ns && nf + (auxJ[s1].l == 0 ? 1 : 3) <= max_f) nf += auxJ[s1++].l == 0 ? 1 : 3;
+      f->ao_s0.push_back(s0);
+      f->ao_f0.push_back(fo);
+      f->ao_max_f = std::max(f->ao_max_f, nf);
+      fo += nf;
+      s0 = s1;
+    }
+    f->ao_s0.push_back(ns);
+    f->ao_f0.push_back(fo);
+    RISP_CHECK(fo == aj.nfunc, RISP_E_STATE, "auxiliary chunk plan does not cover the basis");
+    // trial vectors per group: D_m and U_m slices within 4 GiB
+    f->ao_mg = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4ll << 30) / per_func));
+  } else {
     Operator coul;  // 1/r
     DevBuf Linv;
     metric_inverse_cholesky(ctx, s, aj, coul, Linv);
@@ -448,6 +487,13 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   f->de32.alloc((size_t)nocc * nvir * 4);
   orbital_gaps(E.as<double>(), nocc, nvir, f->de64.as<double>(), f->de32.as<float>(), s);
   RISP_HIP(hipStreamSynchronize(s));
+  if (f->j_mode == RISP_J_AO_DIRECT) {
+    f->ao_sh = std::move(ao);
+    f->auxj_sh = std::move(aj);
+    f->pairs = std::move(pairs);
+    f->co_t = std::move(CoT);
+    f->cv_t = std::move(CvT);
+  }
 }
 
 // -------------------------------------------------------------------------------------------
@@ -455,7 +501,14 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
 // -------------------------------------------------------------------------------------------
 double sigma_flops(const risp_factors* f, int m) {
   const double ov = (double)f->nocc * f->nvir;
-  double fl = 4.0 * ov * f->naux_j * m + ov * m;
+  double fl = ov * m;
+  if (f->j_mode == RISP_J_AO_DIRECT) {
+    // D_m and the back transform (two products each way), both integral contractions, the metric
+    const double nao = f->nao, nJ = f->naux_j;
+    fl += 4.0 * m * (ov * nao + f->nocc * nao * nao + nJ * nao * nao + nJ * nJ);
+  } else {
+    fl += 4.0 * ov * f->naux_j * m;
+  }
   if (f->naux_k > 0)
     fl += 2.0 * f->naux_k * (double)f->nok * f->nvk * m * (double)(f->nok + f->nvk);
   return fl;
@@ -481,11 +534,21 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   m = std::max(m, f->ws_m);
   const int cs = std::max(csz, f->ws_csz);
   const size_t acc = cs == 8 ? 8 : 4;
-  f->ws_y.alloc((size_t)f->naux_j * m * acc);
-  f->ws_ybf.alloc((size_t)kCoulombMaxM * pad_to(f->naux_j, 32) * 2 + 16);
-  f->ws_xbf.alloc((size_t)m * f->ld_ia * 2 + 16);
-  size_t split_bytes = std::max((size_t)kMaxSplit * f->naux_j * m * acc,
-                                coulomb_y_workspace(f->naux_j, std::min(m, kCoulombMaxM), f->ld_ia));
+  size_t split_bytes = 0;
+  if (f->j_mode == RISP_J_AO_DIRECT) {
+    const size_t mg = std::min(m, f->ao_mg), nao = f->nao;
+    f->ws_ao_t.alloc(mg * f->nocc * nao * 8);
+    f->ws_ao_d.alloc(mg * nao * nao * 8);
+    f->ws_ao_v.alloc((size_t)f->ao_max_f * nao * nao * 8);
+    f->ws_ao_r.alloc(2 * (size_t)f->naux_j * mg * 8);
+    split_bytes = (size_t)kMaxSplit * f->ao_max_f * mg * 8;
+  } else {
+    f->ws_y.alloc((size_t)f->naux_j * m * acc);
+    f->ws_ybf.alloc((size_t)kCoulombMaxM * pad_to(f->naux_j, 32) * 2 + 16);
+    f->ws_xbf.alloc((size_t)m * f->ld_ia * 2 + 16);
+    split_bytes = std::max((size_t)kMaxSplit * f->naux_j * m * acc,
+                           coulomb_y_workspace(f->naux_j, std::min(m, kCoulombMaxM), f->ld_ia));
+  }
   if (f->naux_k > 0 && f->nok > 0 && f->nvk > 0) {
     const int64_t per_p = (int64_t)m * f->nvk * f->nokp;
     // room for the chunk of every compute type up to cs bytes per element and every block size up to
@@ -513,6 +576,148 @@ static void need(const DevBuf& b, size_t bytes, const char* what) {
   RISP_CHECK(b.bytes() >= bytes, RISP_E_STATE, std::string("sigma workspace too small: ") + what);
 }
 
+// Coulomb term by the AO-density route (section on on-the-fly Coulomb evaluation), FP64 throughout,
+// for groups of mg trial vectors:
+//   D_m = C_occ X_m C_vir^T;  R_Q = sum_(mu nu) (mu nu|Q) D_m,mu nu;  R~ = L^-T L^-1 R;
+//   U_m = sum_P (mu nu|P) R~_P;  sigma_m = 2 C_occ^T U_m C_vir.
+// (mu nu|P) is regenerated over the screened pairs in each of the two passes; it is symmetric in
+// (mu, nu), so D_m needs no symmetrisation. int3c synchronises the stream.
+static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* sig, int pb, hipStream_t s) {
+  const int nao = f->nao, nocc = f->nocc, nvir = f->nvir, nJ = f->naux_j;
+  const int64_t ov = (int64_t)nocc * nvir, n2 = (int64_t)nao * nao;
+  const size_t vsz = dtype_size(tv);
+  const int nchunk = (int)f->ao_s0.size() - 1;
+  const int mgmax = std::min(m, f->ao_mg);
+  need(f->ws_ao_t, (size_t)mgmax * nocc * nao * 8, "AO half-transformed block");
+  need(f->ws_ao_d, (size_t)mgmax * n2 * 8, "AO densities");
+  need(f->ws_ao_v, (size_t)f->ao_max_f * n2 * 8, "AO integral chunk");
+  need(f->ws_ao_r, 2 * (size_t)nJ * mgmax * 8, "AO auxiliary vectors");
+  double* G = f->ws_ao_t.as<double>();
+  double* D = f->ws_ao_d.as<double>();  // D_m in pass 1, U_m in pass 2
+  double* V = f->ws_ao_v.as<double>();
+  double* R = f->ws_ao_r.as<double>();  // [nJ][mg]
+  double* Yr = R + (size_t)nJ * mgmax;  // [nJ][mg]
+  const double* Linv = f->linv_j.as<double>();
+  for (int g0 = 0; g0 < m; g0 += mgmax) {
+    const int mg = std::min(mgmax, m - g0);
+    {
+      PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y,
+                    2.0 * mg * ((double)ov * nao + (double)nocc * n2 + (double)nJ * n2 + 2.0 * nJ * nJ),
+                    (double)vsz * mg * ov + 8.0 * ((double)nJ * n2 + 2.0 * mg * n2 + (double)nJ * nJ));
+      // G[m][i][nu] = sum_a X[m][i][a] C_vir[nu][a]
+      Gemm a = g64(nocc, nao, nvir);
+      a.mem_a = tv;
+      a.A = static_cast<const char*>(X) + (size_t)g0 * ov * vsz;
+      a.lda = nvir;
+      a.sa2 = ov;
+      a.B = f->cv_t.get();
+      a.ldb = nao;
+      a.b_kc = false;
+      a.C = G;
+      a.ldc = nao;
+      a.sc2 = (int64_t)nocc * nao;
+      a.nb2 = mg;
+      gemm(a, nullptr, s);
+      // D[m][mu][nu] = sum_i C_occ[mu][i] G[m][i][nu]
+      Gemm b = g64(nao, nao, nocc);
+      b.A = f->co_t.get();
+      b.lda = nao;
+      b.a_kc = false;
+      b.B = G;
+      b.ldb = nao;
+      b.b_kc = false;
+      b.sb2 = (int64_t)nocc * nao;
+      b.C = D;
+      b.ldc = nao;
+      b.sc2 = n2;
+      b.nb2 = mg;
+      gemm(b, nullptr, s);
+      // R[Q][m] = sum_(mu nu) (mu nu|Q) D[m][mu nu], chunk by chunk
+      for (int c = 0; c < nchunk; ++c) {
+        const int nf = f->ao_f0[c + 1] - f->ao_f0[c];
+        int3c(f->ao_sh, f->pairs, f->auxj_sh, f->ao_s0[c], f->ao_s0[c + 1], f->j_op, f->ctx->boys.as<double>(), V,
+              s);
+        Gemm r = g64(nf, mg, (int)n2);
+        r.A = V;
+        r.lda = n2;
+        r.B = D;
+        r.ldb = n2;
+        r.C = R + (size_t)f->ao_f0[c] * mg;
+        r.ldc = mg;
+        r.ksplit = std::min(kMaxSplit, gemm_auto_split(r));
+        if (r.ksplit > 1) need(f->ws_split, gemm_workspace_bytes(r), "split-K (AO Coulomb)");
+        gemm(r, r.ksplit > 1 ? f->ws_split.get() : nullptr, s);
+      }
+      // R~ = L^-T (L^-1 R)
+      Gemm l1 = g64(nJ, mg, nJ);
+      l1.A = Linv;
+      l1.lda = nJ;
+      l1.B = R;
+      l1.ldb = mg;
+      l1.b_kc = false;
+      l1.C = Yr;
+      l1.ldc = mg;
+      gemm(l1, nullptr, s);
+      Gemm l2 = g64(nJ, mg, nJ);
+      l2.A = Linv;
+      l2.lda = nJ;
+      l2.a_kc = false;
+      l2.B = Yr;
+      l2.ldb = mg;
+      l2.b_kc = false;
+      l2.C = R;
+      l2.ldc = mg;
+      gemm(l2, nullptr, s);
+    }
+    PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_J,
+                  2.0 * mg * ((double)nJ * n2 + (double)nocc * n2 + (double)ov * nao),
+                  8.0 * ((double)nJ * n2 + 2.0 * mg * n2) + (double)vsz * mg * ov);
+    // U[m][mu nu] = sum_P R~[P][m] (mu nu|P), chunk by chunk (U overwrites D)
+    for (int c = 0; c < nchunk; ++c) {
+      const int nf = f->ao_f0[c + 1] - f->ao_f0[c];
+      int3c(f->ao_sh, f->pairs, f->auxj_sh, f->ao_s0[c], f->ao_s0[c + 1], f->j_op, f->ctx->boys.as<double>(), V, s);
+      Gemm u = g64(mg, (int)n2, nf);
+      u.A = R + (size_t)f->ao_f0[c] * mg;
+      u.lda = mg;
+      u.a_kc = false;
+      u.B = V;
+      u.ldb = n2;
+      u.b_kc = false;
+      u.C = D;
+      u.ldc = n2;
+      u.beta = c > 0 ? 1.0 : 0.0;
+      gemm(u, nullptr, s);
+    }
+    // H[m][i][nu] = sum_mu C_occ[mu][i] U[m][mu][nu]
+    Gemm h = g64(nocc, nao, nao);
+    h.A = f->co_t.get();
+    h.lda = nao;
+    h.B = D;
+    h.ldb = nao;
+    h.b_kc = false;
+    h.sb2 = n2;
+    h.C = G;
+    h.ldc = nao;
+    h.sc2 = (int64_t)nocc * nao;
+    h.nb2 = mg;
+    gemm(h, nullptr, s);
+    // sigma[m][i][a] = 2 sum_nu H[m][i][nu] C_vir[nu][a]
+    Gemm j = g64(nocc, nvir, nao);
+    j.tout = tv;
+    j.A = G;
+    j.lda = nao;
+    j.sa2 = (int64_t)nocc * nao;
+    j.B = f->cv_t.get();
+    j.ldb = nao;
+    j.C = static_cast<char*>(sig) + (size_t)g0 * ov * vsz;
+    j.ldc = nvir;
+    j.sc2 = ov;
+    j.nb2 = mg;
+    j.alpha = 2.0;
+    gemm(j, nullptr, s);
+  }
+}
+
 void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s) {
   if (m <= 0) return;
   const bool bf = f->precision == RISP_BF16 && !use_f32;
@@ -524,17 +729,15 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   const int64_t ov = (int64_t)f->nocc * f->nvir;
   const int nJ = f->naux_j;
   const int64_t ldt = f->ld_ia;  // padded row stride of T_ia
-  need(f->ws_y, (size_t)nJ * m * dtype_size(tacc), "Y");
-  if (bf) {
-    need(f->ws_xbf, (size_t)m * ldt * 2, "X (BF16)");
-    need(f->ws_ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 2, "Yt (BF16)");
-  }
   const void* Tia = (f->precision == RISP_BF16 && use_f32) ? f->t_ia32.get() : f->t_ia.get();
   const void* Tij = (f->precision == RISP_BF16 && use_f32) ? f->t_ij32.get() : f->t_ij.get();
   const void* Tab = (f->precision == RISP_BF16 && use_f32) ? f->t_ab32.get() : f->t_ab.get();
-
   const size_t esz = dtype_size(tc);
-  if (bf) {
+  if (f->j_mode == RISP_J_AO_DIRECT) {
+    coulomb_ao(f, m, X, tv, sig, pb, s);
+  } else if (bf) {
+    need(f->ws_xbf, (size_t)m * ldt * 2, "X (BF16)");
+    need(f->ws_ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 2, "Yt (BF16)");
     // BF16 copy of X with the row stride of T_ia (zero padding), then the two skinny passes
     {
       PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
@@ -562,6 +765,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       }
     }
   } else {
+    need(f->ws_y, (size_t)nJ * m * dtype_size(tacc), "Y");
     // Coulomb pass 1: Y[P][m] = sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
     {
       PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * m,

@@ -70,11 +70,25 @@ struct risp_factors {
   int ws_m = 0;
   int ws_csz = 0;  // bytes per element of the compute type the workspaces were sized for
   risp::DevBuf ws_y, ws_ybf, ws_xbf, ws_xw, ws_mt, ws_k, ws_split;
+  // AO-density Coulomb route (RISP_J_AO_DIRECT): what regenerating (mu nu|P) needs, and workspaces
+  int j_mode = RISP_J_MO;
+  risp::DevShells ao_sh, auxj_sh;
+  risp::PairList pairs;
+  risp::Operator j_op;
+  risp::DevBuf linv_j, co_t, cv_t;  // FP64 L^-1 of the Coulomb metric, C_occ^T [nocc][nao], C_vir^T
+  std::vector<int> ao_s0, ao_f0;     // auxiliary shell / function start of each integral chunk (+ end)
+  int ao_max_f = 0;                  // functions of the largest chunk
+  int ao_mg = 0;                     // trial vectors per group (dense D_m / U_m slices)
+  // workspaces: G / H [ao_mg][nocc][nao], D / U [ao_mg][nao][nao], (mu nu|P) chunk, R and L^-1 R
+  risp::DevBuf ws_ao_t, ws_ao_d, ws_ao_v, ws_ao_r;
   double t_build = 0.0;  // seconds spent in the factor build
   int64_t bytes() const;
 };
 
 namespace risp {
+
+// largest AO basis of the AO Coulomb route: one dense FP64 (mu nu|P) slice is at most 2 GiB
+constexpr int kAoMaxNao = 16384;
 
 // precision of the sigma arithmetic: FP64 factors -> FP64, FP32 -> FP32, BF16 -> BF16 with FP32
 // accumulation; `use_f32` selects the FP32 copies of BF16 factors.

@@ -409,6 +409,8 @@ uint64_t submit_job(risp_ctx* ctx, const risp_system* sys, const risp_params* pr
   RISP_CHECK(prm && opts, RISP_E_ARG, "params and options are required");
   RISP_CHECK(opts->nstates > 0, RISP_E_ARG, "nstates must be positive");
   RISP_CHECK(opts->nx0 == 0, RISP_E_ARG, "initial vectors are not supported for served jobs");
+  RISP_CHECK(prm->j_mode == RISP_J_MO, RISP_E_ARG,
+             "served jobs use the stored-factor Coulomb route (j_mode RISP_J_MO)");
   Server* sv = ensure_server(ctx);
   auto j = std::make_unique<Job>();
   j->coords.assign(sys->coords, sys->coords + 3 * (size_t)sys->natm);

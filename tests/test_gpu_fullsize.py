@@ -67,3 +67,21 @@ def test_energies_vs_oracle_300_atoms(big, prec, tol_e):
     assert info.converged
     assert err.max() <= tol_e
     F.free()
+
+
+def test_sigma_ao_route_300_atoms(big):
+    # the AO-density Coulomb route against the stored-factor route at full size (FP32 exchange and
+    # X / sigma in both; the AO Coulomb term is FP64)
+    mol, ctx, sysc = big
+    import paper_2603_29257_amd as P
+    Fm = ctx.build_factors(sysc, P.Params(precision=P.FP32))
+    Fa = ctx.build_factors(sysc, P.Params(precision=P.FP32, j_mode=P.J_AO_DIRECT))
+    X = torch.tensor(synth.random_trial_vectors(4, Fm.nocc, Fm.nvir, 19), dtype=torch.float32, device=ctx.device)
+    a = ctx.sigma(Fm, X).double()
+    b = ctx.sigma(Fa, X).double()
+    rel = ((b - a).flatten(1).norm(dim=1) / a.flatten(1).norm(dim=1)).max().item()
+    print(f"AO vs stored Coulomb route, 300 atoms, relative norm difference {rel:.3e}; "
+          f"factor bytes {Fa.desc.bytes} vs {Fm.desc.bytes}", flush=True)
+    assert rel <= 1e-5
+    Fm.free()
+    Fa.free()

@@ -274,6 +274,61 @@ def test_davidson_restart_same_answer(ctx, mol0, oracle0):
     F.free()
 
 
+# ---------------------------------------------------------------------------------------------
+# Coulomb term by the AO-density route (no stored T_ia; integrals regenerated per sigma block)
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("m", [1, 7, 70])
+def test_sigma_ao_route_matches_oracle(ctx, mol0, oracle0, prec, m):
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec], j_mode=P.J_AO_DIRECT)
+    assert not F.desc.t_ia
+    with pytest.raises(ValueError):
+        F.tensor("t_ia")
+    X = synth.random_trial_vectors(m, F.nocc, F.nvir, 13)
+    ref = R.sigma_ao(oracle0, mol0, X)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    got = ctx.sigma(F, torch.tensor(X, dtype=dt, device=ctx.device)).cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _print(f"sigma AO route {prec} m={m} max rel err {err:.3e}")
+    # the Coulomb term is FP64 in every precision; FP32 and BF16 errors come from the exchange term
+    # and the FP32 X / sigma
+    tol = {"fp64": 1e-9, "fp32": 2e-6, "bf16": 3e-2}[prec]
+    assert err <= tol
+    F.free()
+
+
+def test_sigma_ao_route_equals_stored_route_fp64(ctx, mol0):
+    import paper_2603_29257_amd as P
+    Fm = _gpu_factors(ctx, mol0, precision=P.FP64)
+    Fa = _gpu_factors(ctx, mol0, precision=P.FP64, j_mode=P.J_AO_DIRECT)
+    X = torch.tensor(synth.random_trial_vectors(5, Fm.nocc, Fm.nvir, 3), dtype=torch.float64, device=ctx.device)
+    a = ctx.sigma(Fm, X).cpu().numpy()
+    b = ctx.sigma(Fa, X).cpu().numpy()
+    err = np.abs(a - b).max() / np.abs(a).max()
+    _print(f"sigma AO vs stored route FP64 max rel diff {err:.3e}")
+    assert err <= 1e-10
+    Fm.free()
+    Fa.free()
+
+
+def test_davidson_ao_route_energies_config0(ctx, mol0, oracle0):
+    import paper_2603_29257_amd as P
+    w, _ = R.lowest_eigh(R.dense_A(oracle0), 5)
+    F = _gpu_factors(ctx, mol0, precision=P.FP32, j_mode=P.J_AO_DIRECT)
+    e, _, info = ctx.davidson(F, 5, tol=1e-5)
+    _print(f"davidson AO route fp32: iters {info.iters} max |dE| {np.abs(e - w).max():.3e}")
+    assert info.converged
+    assert np.abs(e - w).max() <= 1e-6
+    F.free()
+
+
+def test_ao_route_rejected_by_serving(ctx, mol0):
+    import paper_2603_29257_amd as P
+    with pytest.raises(P.RispError):
+        ctx.submit(P.System(mol0), _params(j_mode=P.J_AO_DIRECT), 3)
+
+
 def test_errors_are_reported(ctx, mol0):
     import paper_2603_29257_amd as P
     F = _gpu_factors(ctx, mol0, precision=P.FP32)

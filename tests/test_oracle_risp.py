@@ -166,6 +166,41 @@ def test_sigma_equals_dense_product(tiny):
     assert np.abs(R.sigma(F, 2 * X - Y) - (2 * S - R.sigma(F, Y))).max() <= 1e-13
 
 
+@pytest.mark.parametrize("tau", [0.0, 1e-10])
+def test_coulomb_ao_route_equals_stored_factor_route(tiny, tau):
+    # two different orders of the same contraction: C_occ^T [(mu nu|P)(P|Q)^-1(Q|kl)] C_vir applied
+    # to the AO density C_occ X C_vir^T, against 2 B_ia^T (B_ia X) from the Cholesky-split factors
+    prm = R.Params(schwarz_tau=tau)
+    F = R.build_factors(tiny, prm)
+    X = synth.random_trial_vectors(4, F.nocc, F.nvir, 9)
+    Bf = F.B_ia.reshape(F.B_ia.shape[0], -1)
+    ref = 2.0 * (Bf.T @ (Bf @ X.reshape(4, -1).T)).T.reshape(X.shape)
+    got = R.coulomb_ao(tiny, X, prm)
+    # rounding of the two orders differs by ~1e-12 relative (the metric solve amplifies it); a
+    # dropped or transposed term changes the result at order one
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    # the whole product through the AO route equals the dense matrix
+    S = R.sigma_ao(F, tiny, X, prm)
+    dense = (R.dense_A(F) @ X.reshape(4, -1).T).T.reshape(X.shape)
+    assert np.abs(S - dense).max() <= 1e-11 * np.abs(dense).max()
+
+
+def test_coulomb_ao_route_symmetric_psd_and_linear(tiny):
+    # J is a Gram matrix in the Coulomb metric: symmetric and positive semi-definite, and linear in X
+    prm = R.Params()
+    F = R.build_factors(tiny, prm)
+    X = synth.random_trial_vectors(3, F.nocc, F.nvir, 21)
+    Y = synth.random_trial_vectors(3, F.nocc, F.nvir, 22)
+    JX, JY = R.coulomb_ao(tiny, X, prm), R.coulomb_ao(tiny, Y, prm)
+    scale = np.abs(JX).max() * np.abs(Y).max() * Y[0].size
+    for k in range(3):
+        assert abs(np.sum(Y[k] * JX[k]) - np.sum(X[k] * JY[k])) <= 1e-13 * scale
+        assert np.sum(X[k] * JX[k]) >= 0.0
+    assert np.abs(R.coulomb_ao(tiny, 2 * X - Y, prm) - (2 * JX - JY)).max() <= 1e-11 * np.abs(JX).max()
+    # a zero trial vector gives zero
+    assert np.all(R.coulomb_ao(tiny, np.zeros_like(X[:1]), prm) == 0.0)
+
+
 def test_window_sets_by_hand():
     e = np.array([-2.0, -40.0 / H2EV, -39.0 / H2EV, -0.3, 0.1, 1.0, 40.0 / H2EV, 1.5, 3.0])
     occ, vir = R.window_sets(e, 4, 40.0)
