@@ -120,6 +120,10 @@ typedef struct {
   int32_t nx0;             /* optional initial vectors (resume): count, 0 = unit-vector guess */
   int32_t flags;           /* RISP_DAV_* bits, 0 = none */
   const float *x0;         /* [nx0][nocc*nvir] host */
+  int32_t ncorr;           /* correction vectors per iteration only for the lowest ncorr Ritz pairs
+                              with residual >= tol (at least nstates, at most block); the other
+                              Ritz vectors of the block stay in the subspace; 0 = nstates */
+  int32_t correction_ncorr;/* the same for the FP32 correction stage; 0 = nstates */
 } risp_dav_opts;
 
 /* risp_dav_opts.flags: RISP_DAV_VERBOSE prints one line per iteration (stage, iteration, subspace

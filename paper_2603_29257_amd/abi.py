@@ -60,7 +60,7 @@ class DavOptsC(C.Structure):
     _fields_ = [("nstates", C.c_int32), ("block", C.c_int32), ("max_space", C.c_int32), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("correction_pass", C.c_int32), ("correction_steps", C.c_int32),
                 ("bf16_tol", C.c_double), ("nx0", C.c_int32), ("flags", C.c_int32),
-                ("x0", C.POINTER(C.c_float))]
+                ("x0", C.POINTER(C.c_float)), ("ncorr", C.c_int32), ("correction_ncorr", C.c_int32)]
 
 
 class DavInfoC(C.Structure):
@@ -420,9 +420,9 @@ class Context:
         _check(_LIB.risp_serve_config(self.handle, C.byref(o)))
 
     def submit(self, sys: System, prm: Params, nstates, tol=1e-5, block=0, max_space=0, max_iter=0,
-               correction_pass=True, correction_steps=0, bf16_tol=0.0):
+               correction_pass=True, correction_steps=0, bf16_tol=0.0, ncorr=0, correction_ncorr=0):
         o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
-                     0, 0, None)
+                     0, 0, None, ncorr, correction_ncorr)
         p = prm.c()
         jid = C.c_uint64()
         _check(_LIB.risp_submit(self.handle, C.byref(sys.c), C.byref(p), C.byref(o), C.byref(jid)))
@@ -453,7 +453,8 @@ class Context:
         return {k: getattr(st, k) for k, _ in ServeStatsC._fields_ if k != "reserved"}
 
     def davidson(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, correction_pass=True,
-                 x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0, verbose=False):
+                 x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0, verbose=False,
+                 ncorr=0, correction_ncorr=0):
         ov = F.nocc * F.nvir
         e = np.zeros(nstates)
         vec = np.zeros((nstates, ov), np.float32) if want_vectors else None
@@ -462,7 +463,7 @@ class Context:
             x0a = np.ascontiguousarray(x0, dtype=np.float32).reshape(-1, ov)
         o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
                      0 if x0a is None else x0a.shape[0], DAV_VERBOSE if verbose else 0,
-                     None if x0a is None else _ptr(x0a, C.c_float))
+                     None if x0a is None else _ptr(x0a, C.c_float), ncorr, correction_ncorr)
         info = DavInfoC()
         import torch
         torch.cuda.current_stream(self.device).synchronize()

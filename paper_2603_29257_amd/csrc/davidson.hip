@@ -476,7 +476,8 @@ void DavidsonRun::iterate(Timer& tsub) {
   }
   // corrections for the Ritz pairs not yet converged
   std::vector<int> todo;
-  for (int j = 0; j < k; ++j)
+  const int kc = o_.max_corr > 0 ? std::min(k, std::max(o_.max_corr, nstates_)) : k;
+  for (int j = 0; j < kc; ++j)
     if (hnorm_[j] >= o_.tol) todo.push_back(j);
   const int nt = (int)todo.size();
   RISP_HIP(hipMemcpyAsync(src_.get(), todo.data(), nt * sizeof(int), hipMemcpyHostToDevice, s_));

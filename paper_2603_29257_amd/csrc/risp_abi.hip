@@ -340,6 +340,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
   return guarded([&]() -> risp_status {
     use_ctx(ctx);
     RISP_CHECK(fc && opts && energies, RISP_E_ARG, "NULL argument");
+    RISP_CHECK(opts->ncorr >= 0 && opts->correction_ncorr >= 0, RISP_E_ARG, "ncorr must be non-negative");
     RISP_CHECK(fc->ctx == ctx, RISP_E_STATE, "factors belong to another context");
     risp_factors* f = const_cast<risp_factors*>(fc);
     const int64_t ov = (int64_t)f->nocc * f->nvir;
@@ -350,6 +351,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
     o.max_space = opts->max_space;
     o.max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
     o.tol = opts->tol;
+    o.max_corr = opts->ncorr > 0 ? opts->ncorr : opts->nstates;
     DevBuf x0;
     if (opts->nx0 > 0) {
       RISP_CHECK(opts->x0 != nullptr, RISP_E_ARG, "x0 is NULL");
@@ -386,6 +388,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       oc.x0_dev = r.X.as<double>();
       oc.nx0 = r.krows;
       oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 16);
+      oc.max_corr = opts->correction_ncorr > 0 ? opts->correction_ncorr : opts->nstates;
       SigmaFn f32 = [&](int m, const void* X, void* S) { sigma(f, m, X, S, true, s); };
       davidson(f, oc, f32, rc);
       corr_iters = rc.iters;

@@ -148,6 +148,7 @@ void Server::admit(Job& j) {
   o.max_space = j.opts.max_space;
   o.max_iter = j.opts.max_iter > 0 ? j.opts.max_iter : 200;
   o.tol = j.opts.tol;
+  o.max_corr = j.opts.ncorr > 0 ? j.opts.ncorr : j.opts.nstates;
   if (j.prm.precision == RISP_BF16) {
     if (j.opts.correction_pass) o.tol = std::max(o.tol, j.opts.bf16_tol > 0.0 ? j.opts.bf16_tol : 1e-4);
     o.stall_iters = 8;
@@ -334,6 +335,7 @@ void Server::loop() {
             DavOptions oc;
             oc.nstates = j.opts.nstates;
             oc.block = j.opts.block;
+            oc.max_corr = j.opts.correction_ncorr > 0 ? j.opts.correction_ncorr : j.opts.nstates;
             oc.max_space = j.opts.max_space;
             oc.tol = j.opts.tol;
             oc.x0_dev = j.main_res.X.as<double>();
@@ -409,6 +411,7 @@ uint64_t submit_job(risp_ctx* ctx, const risp_system* sys, const risp_params* pr
   RISP_CHECK(prm && opts, RISP_E_ARG, "params and options are required");
   RISP_CHECK(opts->nstates > 0, RISP_E_ARG, "nstates must be positive");
   RISP_CHECK(opts->nx0 == 0, RISP_E_ARG, "initial vectors are not supported for served jobs");
+  RISP_CHECK(opts->ncorr >= 0 && opts->correction_ncorr >= 0, RISP_E_ARG, "ncorr must be non-negative");
   RISP_CHECK(prm->j_mode == RISP_J_MO, RISP_E_ARG,
              "served jobs use the stored-factor Coulomb route (j_mode RISP_J_MO)");
   Server* sv = ensure_server(ctx);
