@@ -1,7 +1,8 @@
 // Lowest eigenpairs of the FP64 Davidson subspace matrix in one workgroup:
-// Householder reduction to tridiagonal form, bisection on Sturm counts for the k lowest eigenvalues,
-// inverse iteration (tridiagonal LU with partial pivoting) with Gram-Schmidt inside clusters of
-// close eigenvalues, and back-transformation by the stored reflectors.
+// Householder reduction to tridiagonal form, multisection on Sturm counts for the k lowest
+// eigenvalues, inverse iteration (tridiagonal LU with partial pivoting, factored once per eigenvalue)
+// with Gram-Schmidt inside clusters of close eigenvalues, and back-transformation by the stored
+// reflectors.
 #include <cfloat>
 
 #include "subspace.hpp"
@@ -12,93 +13,104 @@ namespace {
 
 constexpr int kThreads = 1024;
 
-__device__ double block_sum(double v, double* red) {
-  // wave64 reduction, then across the 16 waves
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  const int nw = blockDim.x >> 6;
-  for (int w = 0; w < nw; ++w) s += red[w];
-  return s;
-}
-
 __device__ double wave_sum(double v) {  // full sum in every lane of the wave
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-// number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence of LDL^T pivots)
-__device__ int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+constexpr int kMaxN = 1024;  // largest subspace (LDS vectors below)
+
+// number of eigenvalues of the tridiagonal (d, e^2 = e2) below x (Sturm sequence of LDL^T pivots)
+__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   int c = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++c;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    q = d[i] - x - e2[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++c;
   }
   return c;
 }
 
-// One inverse-iteration solve (T - lam I) y = y in place, tridiagonal LU with partial pivoting.
-// Scratch: D, DL, DU, DU2 of length n (one set per thread).
-__device__ void tri_solve(const double* d, const double* e, int n, double lam, double tiny, double* D,
-                          double* DL, double* DU, double* DU2, int* piv_swap, double* y) {
-  for (int i = 0; i < n; ++i) D[i] = d[i] - lam;
+// LU factorisation with partial pivoting of T - lam I (tridiagonal d, e) for one eigenvalue. The
+// factors of the k eigenvalues are interleaved, element i of eigenvalue t at [i * k + t], so a wave's
+// threads touch neighbouring addresses at every step.
+__device__ void tri_factor(const double* d, const double* e, int n, double lam, double tiny, int k, double* D,
+                           double* DL, double* DU, double* DU2, int* sw) {
+  double di = d[0] - lam;  // running diagonal of the current row
+  double ui = n > 1 ? e[0] : 0.0;  // running superdiagonal of the current row
   for (int i = 0; i + 1 < n; ++i) {
-    DL[i] = e[i];
-    DU[i] = e[i];
-  }
-  for (int i = 0; i + 1 < n; ++i) {
-    DU2[i] = 0.0;
-    if (fabs(D[i]) >= fabs(DL[i])) {
-      if (D[i] == 0.0) D[i] = tiny;
-      const double f = DL[i] / D[i];
-      DL[i] = f;
-      D[i + 1] -= f * DU[i];
-      piv_swap[i] = 0;
+    const double l = e[i];               // subdiagonal below row i
+    const double dn = d[i + 1] - lam;    // diagonal of row i + 1
+    const double un = i + 2 < n ? e[i + 1] : 0.0;
+    if (fabs(di) >= fabs(l)) {
+      const double dd = di == 0.0 ? tiny : di;
+      const double f = l / dd;
+      D[i * k] = dd;
+      DU[i * k] = ui;
+      DU2[i * k] = 0.0;
+      DL[i * k] = f;
+      sw[i * k] = 0;
+      di = dn - f * ui;
+      ui = un;
     } else {
-      const double f = D[i] / DL[i];
-      D[i] = DL[i];
-      DL[i] = f;
-      const double t = DU[i];
-      DU[i] = D[i + 1];
-      D[i + 1] = t - f * D[i + 1];
-      if (i + 2 < n) {
-        DU2[i] = DU[i + 1];
-        DU[i + 1] = -f * DU[i + 1];
-      }
-      piv_swap[i] = 1;
+      const double f = di / l;
+      D[i * k] = l;
+      DU[i * k] = dn;
+      DU2[i * k] = un;
+      DL[i * k] = f;
+      sw[i * k] = 1;
+      di = ui - f * dn;
+      ui = -f * un;
     }
   }
-  if (D[n - 1] == 0.0) D[n - 1] = tiny;
-  for (int i = 0; i < n; ++i)
-    if (fabs(D[i]) < tiny) D[i] = D[i] < 0.0 ? -tiny : tiny;
-  // forward: L with row interchanges
+  D[(n - 1) * k] = di == 0.0 ? tiny : di;
+  for (int i = 0; i < n; ++i) {
+    const double v = D[i * k];
+    if (fabs(v) < tiny) D[i * k] = v < 0.0 ? -tiny : tiny;
+  }
+}
+
+// solve with the factors above, y (stride k) in place
+__device__ void tri_solve(int n, int k, const double* D, const double* DL, const double* DU, const double* DU2,
+                          const int* sw, double* y) {
+  double yi = y[0];
   for (int i = 0; i + 1 < n; ++i) {
-    if (piv_swap[i]) {
-      const double t = y[i];
-      y[i] = y[i + 1];
-      y[i + 1] = t - DL[i] * y[i];
+    const double yn = y[(i + 1) * k];
+    if (sw[i * k]) {
+      y[i * k] = yn;
+      yi = yi - DL[i * k] * yn;
     } else {
-      y[i + 1] -= DL[i] * y[i];
+      y[i * k] = yi;
+      yi = yn - DL[i * k] * yi;
     }
   }
-  // back substitution with the upper factor (diagonals D, DU, DU2)
-  y[n - 1] /= D[n - 1];
-  if (n > 1) y[n - 2] = (y[n - 2] - DU[n - 2] * y[n - 1]) / D[n - 2];
-  for (int i = n - 3; i >= 0; --i) y[i] = (y[i] - DU[i] * y[i + 1] - DU2[i] * y[i + 2]) / D[i];
+  y[(n - 1) * k] = yi;
+  double y2 = 0.0, y1 = yi / D[(n - 1) * k];
+  y[(n - 1) * k] = y1;
+  if (n > 1) {
+    const double v = (y[(n - 2) * k] - DU[(n - 2) * k] * y1) / D[(n - 2) * k];
+    y[(n - 2) * k] = v;
+    y2 = y1;
+    y1 = v;
+  }
+  for (int i = n - 3; i >= 0; --i) {
+    const double v = (y[i * k] - DU[i * k] * y1 - DU2[i * k] * y2) / D[i * k];
+    y[i * k] = v;
+    y2 = y1;
+    y1 = v;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H, int n, int ld, int k,
                                                           double* __restrict__ w, double* __restrict__ Z,
                                                           double* __restrict__ ws) {
-  __shared__ double red[kThreads / 64];
-  __shared__ double sh_beta, sh_alpha, sh_K;
+  __shared__ double sv[kMaxN], sp[kMaxN];  // current reflector and b A v; later d and e^2
+  __shared__ double se[kMaxN];             // e (off-diagonal) for the bisection / inverse iteration
+  __shared__ int scnt[kThreads];
+  __shared__ double sh_beta, sh_alpha;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
   double* V = ws;                      // reflectors: row j holds v_j[0..n-j-2]
@@ -107,60 +119,61 @@ __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H
   double* beta = e + n;                // reflector scales
   double* p = beta + n;                // work vector (length n >= k)
   double* Y = p + n;                   // [n][k] eigenvectors of the tridiagonal
-  double* S = Y + (size_t)n * k;       // per-eigenvalue scratch: 5 n doubles each
-  int* piv = reinterpret_cast<int*>(S + (size_t)5 * n * k);  // per-eigenvalue n ints
+  double* S = Y + (size_t)n * k;       // LU factors, 4 arrays [n][k]
+  int* piv = reinterpret_cast<int*>(S + (size_t)4 * n * k);  // [n][k] row interchanges
 
   // ---- Householder tridiagonalisation (full symmetric storage, lower reflectors) ----
+  // per step: wave 0 forms the reflector, all waves form p = b A22 v, then every wave forms
+  // K = b v.p / 2 itself and applies A22 -= v q^T + q v^T with q = p - K v
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;
     const double* x = H + (size_t)j * ld + j + 1;  // row j right of the diagonal = column j below
-    double s = 0.0;
-    for (int c = tid; c < m; c += nt) s += x[c] * x[c];
-    s = block_sum(s, red);
-    if (tid == 0) {
+    if (wave == 0) {
+      double s = 0.0;
+      for (int c = lane; c < m; c += 64) s += x[c] * x[c];
+      s = wave_sum(s);
       const double x0 = x[0];
       const double rest = s - x0 * x0;
-      if (rest <= 0.0) {  // already reduced
-        sh_beta = 0.0;
-        sh_alpha = x0;
-      } else {
-        const double alpha = x0 >= 0.0 ? -sqrt(s) : sqrt(s);
+      double b = 0.0, alpha = x0;
+      if (rest > 0.0) {
+        alpha = x0 >= 0.0 ? -sqrt(s) : sqrt(s);
         const double v0 = x0 - alpha;
-        sh_beta = 2.0 / (rest + v0 * v0);
-        sh_alpha = alpha;
+        b = 2.0 / (rest + v0 * v0);
       }
-      d[j] = H[(size_t)j * ld + j];
-      e[j] = sh_alpha;
-      beta[j] = sh_beta;
+      for (int c = lane; c < m; c += 64) {
+        const double vc = c == 0 ? x0 - alpha : x[c];
+        sv[c] = vc;
+        V[(size_t)j * n + c] = vc;
+      }
+      if (lane == 0) {
+        sh_beta = b;
+        sh_alpha = alpha;
+        d[j] = H[(size_t)j * ld + j];
+        e[j] = alpha;
+        beta[j] = b;
+      }
     }
     __syncthreads();
     const double b = sh_beta;
-    double* v = V + (size_t)j * n;
-    for (int c = tid; c < m; c += nt) v[c] = (c == 0) ? x[0] - sh_alpha : x[c];
-    __syncthreads();
-    if (b == 0.0) continue;
-    // p = b A22 v (one wave per row, lanes over columns)
+    if (b == 0.0) {  // uniform; the barrier keeps wave 0 from overwriting sh_beta before all read it
+      __syncthreads();
+      continue;
+    }
     for (int r = wave; r < m; r += nwave) {
       const double* row = H + (size_t)(j + 1 + r) * ld + j + 1;
       double acc = 0.0;
-      for (int c = lane; c < m; c += 64) acc += row[c] * v[c];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-      if (lane == 0) p[r] = b * acc;
+      for (int c = lane; c < m; c += 64) acc += row[c] * sv[c];
+      acc = wave_sum(acc);
+      if (lane == 0) sp[r] = b * acc;
     }
     __syncthreads();
     double kk = 0.0;
-    for (int r = tid; r < m; r += nt) kk += v[r] * p[r];
-    kk = block_sum(kk, red);
-    if (tid == 0) sh_K = 0.5 * b * kk;
-    __syncthreads();
-    const double K = sh_K;
-    for (int r = tid; r < m; r += nt) p[r] -= K * v[r];  // q
-    __syncthreads();
-    // A22 -= v q^T + q v^T  (one wave per row)
+    for (int c = lane; c < m; c += 64) kk += sv[c] * sp[c];
+    const double K = 0.5 * b * wave_sum(kk);
     for (int r = wave; r < m; r += nwave) {
       double* row = H + (size_t)(j + 1 + r) * ld + j + 1;
-      const double vr = v[r], pr = p[r];
-      for (int c = lane; c < m; c += 64) row[c] -= vr * p[c] + pr * v[c];
+      const double vr = sv[r], qr = sp[r] - K * sv[r];
+      for (int c = lane; c < m; c += 64) row[c] -= vr * (sp[c] - K * sv[c]) + qr * sv[c];
     }
     __syncthreads();
   }
@@ -174,59 +187,84 @@ __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H
     beta[n - 1] = 0.0;
   }
   __syncthreads();
+  // tridiagonal into LDS: sv = d, sp = e^2, se = e
+  for (int i = tid; i < n; i += nt) {
+    sv[i] = d[i];
+    const double ei = i + 1 < n ? e[i] : 0.0;
+    se[i] = ei;
+    sp[i] = ei * ei;
+  }
+  __syncthreads();
+  const double* dd = sv;
+  const double* e2 = sp;
+  const double* ee = se;
 
-  // ---- bisection for the k lowest eigenvalues ----
+  // ---- multisection for the k lowest eigenvalues ----
+  // G threads per eigenvalue evaluate Sturm counts at G interior points of its interval and the
+  // interval shrinks to the subinterval where the count passes the eigenvalue's index
   double tnorm = 0.0, emax2 = 0.0;
-  double lo = 0.0, hi = 0.0;
-  {
-    lo = d[0];
-    hi = d[0];
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
-      lo = fmin(lo, d[i] - r);
-      hi = fmax(hi, d[i] + r);
-      tnorm = fmax(tnorm, fabs(d[i]) + r);
-      if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
-    }
+  double lo = dd[0], hi = dd[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+    lo = fmin(lo, dd[i] - r);
+    hi = fmax(hi, dd[i] + r);
+    tnorm = fmax(tnorm, fabs(dd[i]) + r);
+    if (i + 1 < n) emax2 = fmax(emax2, e2[i]);
   }
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
   const double eps = DBL_EPSILON;
   const double span = fmax(hi - lo, tnorm * eps);
   lo -= 2.0 * eps * span + pivmin;
   hi += 2.0 * eps * span + pivmin;
-  if (tid < k) {
-    double a = lo, bnd = hi;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (a + bnd);
-      if (bnd - a <= 2.0 * eps * fmax(fabs(a), fabs(bnd)) + pivmin) break;
-      if (sturm_count(d, e, n, mid, pivmin) > tid) bnd = mid;
-      else a = mid;
+  const int G = nt / k;  // >= 1 (k <= kThreads)
+  const int t_ev = tid / G, g = tid % G;
+  const bool act = t_ev < k;
+  double a = lo, bnd = hi;
+  for (int it = 0; it < 100; ++it) {
+    // every thread of a group holds the same interval; the stop test is uniform per group
+    const bool open = act && !(bnd - a <= 2.0 * eps * fmax(fabs(a), fabs(bnd)) + pivmin);
+    if (open) scnt[tid] = sturm_count(dd, e2, n, a + (bnd - a) * (double)(g + 1) / (double)(G + 1), pivmin);
+    __syncthreads();
+    int any = 0;
+    if (open) {
+      // first point whose count exceeds the index: the eigenvalue lies below it
+      int q = G;
+      for (int u = 0; u < G; ++u)
+        if (scnt[t_ev * G + u] > t_ev) {
+          q = u;
+          break;
+        }
+      const double na = q == 0 ? a : a + (bnd - a) * (double)q / (double)(G + 1);
+      const double nb = q == G ? bnd : a + (bnd - a) * (double)(q + 1) / (double)(G + 1);
+      a = na;
+      bnd = nb;
+      any = 1;
     }
-    w[tid] = 0.5 * (a + bnd);
+    if (!__syncthreads_or(any)) break;
   }
+  if (act && g == 0) w[t_ev] = 0.5 * (a + bnd);
   __syncthreads();
 
-  // ---- inverse iteration ----
+  // ---- inverse iteration: one factorisation per eigenvalue, three solves ----
   const double tiny = eps * fmax(tnorm, DBL_MIN);
   const double ortol = 1e-3 * tnorm;
+  double* fD = S;
+  double* fDL = S + (size_t)n * k;
+  double* fDU = S + (size_t)2 * n * k;
+  double* fDU2 = S + (size_t)3 * n * k;
+  if (tid < k) {
+    tri_factor(dd, ee, n, w[tid], tiny, k, fD + tid, fDL + tid, fDU + tid, fDU2 + tid, piv + tid);
+    for (int i = 0; i < n; ++i) Y[(size_t)i * k + tid] = 1.0 + 0.25 * sin(0.7 * (i + 1) * (tid + 1));
+  }
   for (int round = 0; round < 3; ++round) {
     if (tid < k) {
-      double* sD = S + (size_t)5 * n * tid;
-      double* sDL = sD + n;
-      double* sDU = sD + 2 * n;
-      double* sDU2 = sD + 3 * n;
-      double* col = sD + 4 * n;
       double* yy = Y + tid;  // column tid, stride k
-      if (round == 0) {
-        for (int i = 0; i < n; ++i) col[i] = 1.0 + 0.25 * sin(0.7 * (i + 1) * (tid + 1));
-      } else {
-        for (int i = 0; i < n; ++i) col[i] = yy[(size_t)i * k];
-      }
-      tri_solve(d, e, n, w[tid], tiny, sD, sDL, sDU, sDU2, piv + (size_t)n * tid, col);
+      tri_solve(n, k, fD + tid, fDL + tid, fDU + tid, fDU2 + tid, piv + tid, yy);
       double nrm = 0.0;
-      for (int i = 0; i < n; ++i) nrm += col[i] * col[i];
+      for (int i = 0; i < n; ++i) nrm += yy[(size_t)i * k] * yy[(size_t)i * k];
       nrm = sqrt(nrm);
-      for (int i = 0; i < n; ++i) yy[(size_t)i * k] = nrm > 0.0 ? col[i] / nrm : 0.0;
+      const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      for (int i = 0; i < n; ++i) yy[(size_t)i * k] *= inv;
     }
     __syncthreads();
     // Gram-Schmidt inside clusters of close eigenvalues (in ascending order), by the first wave
@@ -263,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H
     for (int t = wave; t < k; t += nwave) {
       double acc = 0.0;
       for (int c = lane; c < m; c += 64) acc += v[c] * Y[(size_t)(j + 1 + c) * k + t];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+      acc = wave_sum(acc);
       if (lane == 0) p[t] = b * acc;
     }
     __syncthreads();
@@ -281,12 +319,13 @@ __global__ __launch_bounds__(kThreads) void k_syev_lowest(double* __restrict__ H
 }  // namespace
 
 size_t subspace_eig_workspace(int n, int k) {
-  return sizeof(double) * ((size_t)n * n + 4 * (size_t)n + (size_t)n * k + 5 * (size_t)n * k) +
+  return sizeof(double) * ((size_t)n * n + 4 * (size_t)n + (size_t)n * k + 4 * (size_t)n * k) +
          sizeof(int) * (size_t)n * k + 64;
 }
 
 void subspace_eig(double* H, int n, int ld, int k, double* w, double* Z, double* ws, hipStream_t s) {
-  RISP_CHECK(n >= 1 && k >= 1 && k <= n && k <= kThreads && ld >= n, RISP_E_ARG, "subspace_eig: bad sizes");
+  RISP_CHECK(n >= 1 && k >= 1 && k <= n && k <= kThreads && n <= kMaxN && ld >= n, RISP_E_ARG,
+             "subspace_eig: bad sizes");
   k_syev_lowest<<<1, kThreads, 0, s>>>(H, n, ld, k, w, Z, ws);
   RISP_LAUNCHED();
 }
