@@ -297,6 +297,14 @@ size_t gemm_workspace_bytes(const Gemm& g) {
 
 int gemm_auto_split(const Gemm& g) {
   const bool f64 = g.tin == DType::F64;
+  if (f64 && gemm_bf16_nt_eligible(g)) {
+    // 128 x 256 tiles, one block per CU: aim for at least two waves of blocks over 256 CUs
+    const int64_t tiles = (int64_t)((g.M + 127) / 128) * ((g.N + 255) / 256) * g.nb1 * g.nb2;
+    if (tiles >= 512) return 1;
+    int64_t split = (512 + tiles - 1) / tiles;
+    split = std::min<int64_t>(split, std::max(1, g.K / (8 * 16)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(split, 4096));
+  }
   if (gemm_bf16_nt_eligible(g)) {
     // large tiles, one block per CU: aim for at least four waves of blocks over 256 CUs
     Gemm h = g;
@@ -342,6 +350,14 @@ void gemm(const Gemm& g, void* work, hipStream_t s) {
                "gemm: FP64 products read FP64 or FP32 operands");
     RISP_CHECK(g.tout == DType::F64 || g.tout == DType::F32, RISP_E_ARG, "gemm: FP64 products write FP64/FP32");
     const bool o64 = g.tout == DType::F64;
+    if (gemm_bf16_nt_eligible(g)) {
+      gemm_bf16_nt(g, work, s);
+      if (g.ksplit > 1) {
+        if (o64) reduce_split<double, double>(g, work, s);
+        else reduce_split<double, float>(g, work, s);
+      }
+      return;
+    }
     if (ma == DType::F64 && mb == DType::F64) {
       if (o64) launch<double, double, double, double>(g, work, s);
       else launch<double, double, double, float>(g, work, s);

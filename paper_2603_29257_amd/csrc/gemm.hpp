@@ -50,8 +50,9 @@ struct Gemm {
 size_t gemm_workspace_bytes(const Gemm& g);
 void gemm(const Gemm& g, void* work, hipStream_t s);
 
-// Tuned BF16 kernel for contraction-contiguous operands (used by gemm() when eligible: BF16
-// products, F32/BF16 output, 16-byte aligned operands, strides and K multiples of 8).
+// Tuned kernel for contraction-contiguous operands (used by gemm() when eligible: BF16 products
+// with F32/BF16 output, FP32 products of FP32 data, FP64 products of FP64 data with FP64/FP32
+// output; 16-byte aligned operands, strides and K multiples of 16 bytes).
 bool gemm_bf16_nt_eligible(const Gemm& g);
 int gemm_bf16_nt_tile(const Gemm& g);  // rows of the output tile it would use (128, 192, 256)
 void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s);

@@ -1,5 +1,5 @@
-// Products with both operands stored contraction-contiguous (C = A . B^T), BF16 or FP32 operands:
-// the exchange products of sigma and the plain FP32 path.
+// Products with both operands stored contraction-contiguous (C = A . B^T), BF16, FP32 or FP64
+// operands: the exchange products of sigma, the plain FP32 path and the FP64 factor transforms.
 //
 // One 512-thread block (8 wave64s in a 2 x 4 grid, two per SIMD) computes a BM x 256 tile,
 // BM = 64 * TI (128, 192 or 256); each wave owns a (BM/2) x 64 sub-tile of TI x 2 32x32 MFMA
@@ -220,6 +220,152 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
     }
 }
 
+// FP64 products (factor build): the same loader, LDS stages and XCD renumbering with a 128 x 256
+// tile; each wave owns a 64 x 64 sub-tile of 4 x 4 v_mfma_f64_16x16x4_f64 accumulators. A 128-byte
+// slice holds 16 k values; lane group q = lane / 16 reads chunk 4 s + q (two k values) in step
+// s = 0, 1 and feeds them to two consecutive MFMAs, so the k values of one MFMA are 8 s + 2 q + e
+// for e = 0, 1 (a permutation of the slice, the same for A and B).
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename TO>
+__global__ __launch_bounds__(NT, 1) void k_gemm_nt64(Gemm g, int tiles_m, int tiles_n, double* __restrict__ work) {
+  constexpr int ES = 8, BK = ROWB / ES, EPC = 2;
+  constexpr int BM = 128, ROWS = BM + BN, NLD = ROWS / RSTEP, STAGE = ROWS * ROWB;
+  constexpr int FM = BM / 2 / 16, FN = WN / 16;
+  __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
+
+  const int W = gridDim.x, w = blockIdx.x;
+  const int per = (W + 7) / 8, tall = (W % 8 == 0) ? 8 : W % 8, x = w % 8, qb8 = w / 8;
+  const int L = x < tall ? x * per + qb8 : tall * per + (x - tall) * (per - 1) + qb8;
+  const int tiles = tiles_m * tiles_n;
+  const int zb = L / tiles, t = L % tiles;
+  const int tm = t % tiles_m, tn = t / tiles_m;
+  const int split = zb % g.ksplit, b = zb / g.ksplit;
+  const int b1 = b / g.nb2, b2 = b % g.nb2;
+  const double* A = static_cast<const double*>(g.A) + b1 * g.sa1 + b2 * g.sa2;
+  const double* B = static_cast<const double*>(g.B) + b1 * g.sb1 + b2 * g.sb2;
+  const int m0 = tm * BM, n0 = tn * BN;
+  int kbeg = 0, kend = g.K;
+  if (g.ksplit > 1) {
+    const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+    kbeg = split * kchunk;
+    kend = min(g.K, kbeg + kchunk);
+  }
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+
+  const int tid = threadIdx.x;
+  const int r_t = tid >> 3, c_t = tid & 7;
+  const int st_off = r_t * ROWB + 16 * (c_t ^ ((r_t >> 1) & 7));
+  const int rows_a = max(0, min(BM, g.M - m0)), rows_b = max(0, min(BN, g.N - n0));
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + (int64_t)m0 * g.lda, (int)((int64_t)rows_a * g.lda * ES));
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + (int64_t)n0 * g.ldb, (int)((int64_t)rows_b * g.ldb * ES));
+  const uint32_t va = (uint32_t)((r_t * g.lda + EPC * c_t) * ES), vb = (uint32_t)((r_t * g.ldb + EPC * c_t) * ES);
+  const uint32_t qa = (uint32_t)(RSTEP * g.lda * ES), qbs = (uint32_t)(RSTEP * g.ldb * ES);
+
+  uint4 reg[NLD];
+  auto gload = [&](int kt) {
+    const int k0 = kbeg + kt * BK;
+    const bool kin = k0 + EPC * c_t < kend;
+#pragma unroll
+    for (int qq = 0; qq < NLD; ++qq) {
+      const bool isA = qq < BM / RSTEP;
+      const uint32_t off = isA ? va + qq * qa + ES * k0 : vb + (qq - BM / RSTEP) * qbs + ES * k0;
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(isA ? ra : rb, kin ? off : 0x80000000u, 0, 0);
+      __builtin_memcpy(&reg[qq], &v, 16);
+    }
+  };
+  auto sstore = [&](int stage) {
+    char* base = lds + stage * STAGE + st_off;
+#pragma unroll
+    for (int qq = 0; qq < NLD; ++qq) *reinterpret_cast<uint4*>(base + qq * RSTEP * ROWB) = reg[qq];
+  };
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * WN;
+  const int l16 = lane & 15, q = lane >> 4, swz = (l16 >> 1) & 7;
+  const int a_off = (wm + l16) * ROWB, b_off = (BM + wn + l16) * ROWB;
+
+  d4v acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+
+  if (nk > 0) {
+    gload(0);
+    sstore(0);
+    if (nk > 1) gload(1);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const char* buf = lds + (kt & 1) * STAGE;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int chunk = 16 * ((4 * st + q) ^ swz);
+      double2 a[FM], bb[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const double2*>(buf + a_off + i * 16 * ROWB + chunk);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bb[j] = *reinterpret_cast<const double2*>(buf + b_off + j * 16 * ROWB + chunk);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, bb[j].x, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, bb[j].y, acc[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore((kt + 1) & 1);
+    if (kt + 2 < nk) gload(kt + 2);
+    __syncthreads();
+  }
+
+  // accumulator element r of lane l: row l / 16 + 4 r, column l % 16 of its 16 x 16 fragment
+  if (g.ksplit > 1) {
+    double* Wp = work + ((int64_t)b * g.ksplit + split) * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + q + 4 * r;
+        if (row >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int col = n0 + wn + j * 16 + l16;
+          if (col < g.N) Wp[(int64_t)row * g.N + col] = acc[i][j][r];
+        }
+      }
+    return;
+  }
+  TO* C = static_cast<TO*>(g.C) + b1 * g.sc1 + b2 * g.sc2;
+  const double bs = g.alpha * (g.batch_scale ? (double)g.batch_scale[b2] : 1.0);
+  int64_t coff[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int col = n0 + wn + j * 16 + l16;
+    coff[j] = col < g.N ? col_offset(g, col) : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + wm + i * 16 + q + 4 * r;
+      if (row >= g.M) continue;
+      const double rs = g.row_scale ? bs * (double)g.row_scale[row] : bs;
+      TO* crow = C + (int64_t)row * g.ldc;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        if (coff[j] < 0) continue;
+        TO* cp = crow + coff[j];
+        double v = rs * acc[i][j][r];
+        if (g.beta != 0.0) v += g.beta * (double)*cp;
+        *cp = (TO)v;
+      }
+    }
+}
+
 template <int TI>
 void launch_ti(const Gemm& g, void* work, hipStream_t s) {
   constexpr int BM = 64 * TI;
@@ -243,8 +389,10 @@ bool gemm_bf16_nt_eligible(const Gemm& g) {
   const DType ma = g.mem_a == DType::Same ? g.tin : g.mem_a, mb = g.mem_b == DType::Same ? g.tin : g.mem_b;
   const bool bf = g.tin == DType::BF16 && (g.tout == DType::F32 || g.tout == DType::BF16);
   const bool f32 = g.tin == DType::F32 && ma == DType::F32 && mb == DType::F32 && g.tout == DType::F32;
-  if (!(bf || f32) || !g.a_kc || !g.b_kc) return false;
-  const int64_t es = bf ? 2 : 4, epc = 16 / es;  // element bytes, elements per 16-byte chunk
+  const bool f64 = g.tin == DType::F64 && ma == DType::F64 && mb == DType::F64 &&
+                   (g.tout == DType::F64 || g.tout == DType::F32);
+  if (!(bf || f32 || f64) || !g.a_kc || !g.b_kc) return false;
+  const int64_t es = bf ? 2 : (f32 ? 4 : 8), epc = 16 / es;  // element bytes, elements per 16-byte chunk
   const bool aligned = (reinterpret_cast<uintptr_t>(g.A) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0);
   const bool strides = g.lda % epc == 0 && g.ldb % epc == 0 && g.sa1 % epc == 0 && g.sa2 % epc == 0 &&
                        g.sb1 % epc == 0 && g.sb2 % epc == 0 && g.K % epc == 0;
@@ -255,6 +403,7 @@ bool gemm_bf16_nt_eligible(const Gemm& g) {
 }
 
 int gemm_bf16_nt_tile(const Gemm& g) {
+  if (g.tin == DType::F64) return 128;
   // pick BM in {256, 192, 128}: fraction of useful rows x fill of the last wave of blocks x
   // relative per-tile throughput of the narrower tiles (fewer MFMAs per LDS byte)
   const int64_t nz = (int64_t)g.nb1 * g.nb2 * g.ksplit;
@@ -278,6 +427,16 @@ int gemm_bf16_nt_tile(const Gemm& g) {
 }
 
 void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s) {
+  if (g.tin == DType::F64) {
+    const int tm = (g.M + 127) / 128, tn = (g.N + BN - 1) / BN;
+    const int64_t blocks = (int64_t)tm * tn * g.nb1 * g.nb2 * g.ksplit;
+    RISP_CHECK(blocks < (1ll << 31), RISP_E_SHAPE, "gemm grid too large");
+    double* w = static_cast<double*>(work);
+    if (g.tout == DType::F64) k_gemm_nt64<double><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+    else k_gemm_nt64<float><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+    RISP_LAUNCHED();
+    return;
+  }
   switch (gemm_bf16_nt_tile(g)) {
     case 256: launch_ti<4>(g, work, s); break;
     case 192: launch_ti<3>(g, work, s); break;
