@@ -162,6 +162,10 @@ typedef struct {
   int64_t ld_ia;          /* row stride of t_ia: nocc*nvir rounded up to a multiple of 8 (t_ia is
                              NULL for factors built with RISP_J_AO_DIRECT) */
   int32_t ld_ij, ld_ab;   /* row strides of t_ij and t_ab: nocc_k, nvir_k rounded up likewise */
+  const double *diag_a;   /* dev [nocc][nvir] FP64 diagonal of A from the FP64 factors before
+                             storage: e_a - e_i + 2 sum_P B_ia^2 - [window] sum_P Bx_ii Bx_aa (the
+                             Coulomb part is left out on the AO route); Davidson guess and
+                             preconditioner */
 } risp_factors_desc;
 
 /* Per-phase timing of sigma products (HIP events on the context stream around each launch). */

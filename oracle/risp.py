@@ -238,6 +238,16 @@ def dense_A(F: Factors) -> np.ndarray:
     return A
 
 
+def diag_A(F: Factors) -> np.ndarray:
+    """Diagonal of A [nocc][nvir]: e_a - e_i + 2 sum_P B^P_ia^2 - [i in occK', a in virK'] sum_P Bx^P_ii Bx^P_aa."""
+    d = F.de + 2.0 * np.einsum("Pia,Pia->ia", F.B_ia, F.B_ia)
+    if F.Bx_ij.shape[0]:
+        bii = np.einsum("Pii->Pi", F.Bx_ij)
+        baa = np.einsum("Paa->Pa", F.Bx_ab)
+        d[np.ix_(F.occK, F.virK)] -= bii.T @ baa
+    return d
+
+
 def sigma(F: Factors, X: np.ndarray, coulomb=None) -> np.ndarray:
     """sigma = A X for a block X [m][nocc][nvir], matrix-free.
 

@@ -86,7 +86,7 @@ class FactorsDescC(C.Structure):
                 ("npair", C.c_int32), ("precision", C.c_int32), ("bytes", C.c_int64),
                 ("t_ia", C.c_void_p), ("t_ij", C.c_void_p), ("t_ab", C.c_void_p), ("scale_ia", C.c_void_p),
                 ("scale_k", C.c_void_p), ("occ_k", C.c_void_p), ("vir_k", C.c_void_p),
-                ("ld_ia", C.c_int64), ("ld_ij", C.c_int32), ("ld_ab", C.c_int32)]
+                ("ld_ia", C.c_int64), ("ld_ij", C.c_int32), ("ld_ab", C.c_int32), ("diag_a", C.c_void_p)]
 
 
 class ServeOptsC(C.Structure):
@@ -260,7 +260,7 @@ class Factors:
         shapes = {"t_ia": ((d.naux_j, d.ld_ia), dt), "t_ij": ((d.nocc_k, d.naux_k, d.ld_ij), dt),
                   "t_ab": ((d.naux_k, d.nvir_k, d.ld_ab), dt), "scale_ia": ((d.naux_j,), torch.float32),
                   "scale_k": ((d.naux_k,), torch.float32), "occ_k": ((d.nocc_k,), torch.int32),
-                  "vir_k": ((d.nvir_k,), torch.int32)}
+                  "vir_k": ((d.nvir_k,), torch.int32), "diag_a": ((d.nocc, d.nvir), torch.float64)}
         shape, dtype = shapes[which]
         ptr = getattr(d, which)
         if which == "t_ia" and not ptr and d.naux_j > 0:

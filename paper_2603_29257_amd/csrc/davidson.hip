@@ -64,7 +64,8 @@ __global__ void k_residual(double* __restrict__ AX, const double* __restrict__ X
     AX[t] -= theta[t / ov] * X[t];
 }
 
-// T[r][ia] = R[src[r]][ia] / (theta[src[r]] - de[ia]), |denominator| floored at 1e-8 (sign kept)
+// T[r][ia] = R[src[r]][ia] / (theta[src[r]] - de[ia]) with de the diagonal of A, |denominator|
+// floored at 1e-8 (sign kept)
 __global__ void k_precond(const double* __restrict__ R, const double* __restrict__ theta,
                           const double* __restrict__ de, const int* __restrict__ src, int nt, int64_t ov,
                           double* __restrict__ T) {
@@ -234,9 +235,10 @@ DavidsonRun::DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s) : 
     store_T(0, nk);
     rq_ = {0, nk};
   } else {
-    // unit vectors at the lowest e_a - e_i, ties broken by (i, a)
+    // unit vectors at the lowest diagonal elements of A, ties broken by (i, a)
     std::vector<double> de(ov);
-    RISP_HIP(hipMemcpyAsync(de.data(), f->de64.get(), ov * 8, hipMemcpyDeviceToHost, s_));
+    RISP_HIP(hipMemcpyAsync(de.data(), f->diag64.get() ? f->diag64.get() : f->de64.get(), ov * 8,
+                            hipMemcpyDeviceToHost, s_));
     RISP_HIP(hipStreamSynchronize(s_));
     std::vector<int> idx(ov);
     std::iota(idx.begin(), idx.end(), 0);
@@ -481,7 +483,8 @@ void DavidsonRun::iterate(Timer& tsub) {
     if (hnorm_[j] >= o_.tol) todo.push_back(j);
   const int nt = (int)todo.size();
   RISP_HIP(hipMemcpyAsync(src_.get(), todo.data(), nt * sizeof(int), hipMemcpyHostToDevice, s_));
-  k_precond<<<grid_for((int64_t)nt * ov), 256, 0, s_>>>(AX_.as<double>(), theta_.as<double>(), f_->de64.as<double>(),
+  const double* dg = f_->diag64.get() ? f_->diag64.as<double>() : f_->de64.as<double>();
+  k_precond<<<grid_for((int64_t)nt * ov), 256, 0, s_>>>(AX_.as<double>(), theta_.as<double>(), dg,
                                                         src_.as<int>(), nt, ov, T_.as<double>());
   RISP_LAUNCHED();
   row_norms(T_.as<double>(), nt, norms_.as<double>());

@@ -16,7 +16,7 @@ static size_t shell_bytes(const risp::DevShells& d) {
 int64_t risp_factors::bytes() const {
   return (int64_t)(t_ia.bytes() + t_ij.bytes() + t_ab.bytes() + t_ia32.bytes() + t_ij32.bytes() +
                    t_ab32.bytes() + scale_ia.bytes() + scale_ia2.bytes() + scale_k.bytes() + occ_k.bytes() +
-                   vir_k.bytes() + pos_o.bytes() + pos_v.bytes() + de64.bytes() + de32.bytes() +
+                   vir_k.bytes() + pos_o.bytes() + pos_v.bytes() + de64.bytes() + de32.bytes() + diag64.bytes() +
                    ws_y.bytes() + ws_ybf.bytes() + ws_xbf.bytes() + ws_xw.bytes() + ws_mt.bytes() +
                    ws_k.bytes() + ws_split.bytes() + shell_bytes(ao_sh) + shell_bytes(auxj_sh) + pairs.a.bytes() +
                    pairs.b.bytes() + linv_j.bytes() + co_t.bytes() + cv_t.bytes() + ws_ao_t.bytes() +
@@ -318,6 +318,8 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   // over every chunk, and the BF16 rows are written from the FP32 copy at the end.
   const bool bf = prm->precision == RISP_BF16;
   const DType tdst = prm->precision == RISP_FP64 ? DType::F64 : DType::F32;
+  f->diag64.alloc((size_t)std::max<int64_t>((int64_t)nocc * nvir, 1) * 8);
+  fill_zero(f->diag64.get(), f->diag64.bytes(), s);
   RISP_CHECK(prm->build_chunk_kib >= 0, RISP_E_ARG, "build_chunk_kib must be non-negative");
   const int64_t chunk_bytes = prm->build_chunk_kib > 0 ? ((int64_t)prm->build_chunk_kib << 10) : kBuildChunk;
   const size_t dsz = dtype_size(tdst);
@@ -368,6 +370,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       transformed_3c(ctx, s, ao, pairs, aj, coul, CoT.as<double>() + (size_t)i0 * nao, nic, CvT.as<double>(), nvir,
                      Tt.as<double>());
       metric_apply_inplace(Linv.as<double>(), nJ, Tt.as<double>(), cols, tmp, s);
+      col_sumsq(Tt.as<double>(), nJ, cols, cols, 2.0, f->diag64.as<double>() + (size_t)i0 * nvir, s);
       if (bf) row_absmax(Tt.as<double>(), nJ, cols, cols, mx.as<double>(), i0 > 0, s);
       store_block(Tt.get(), DType::F64, cols, 0, static_cast<char*>(dst.get()) + (size_t)i0 * nvir * dsz, tdst,
                   f->ld_ia, 0, 1, nJ, cols, s);
@@ -424,6 +427,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     dab.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * dsz);
     fill_zero(dab.get(), dab.bytes(), s);
     DevBuf mxab((size_t)std::max(nK, 1) * 8), tmp;
+    DevBuf Baa((size_t)nK * nvk * 8);  // Bx^P_aa, for the diagonal of A
     const int64_t na = std::max<int64_t>(1, std::min<int64_t>(nvk, chunk_bytes / ((int64_t)nks * nvk * 8)));
     DevBuf Bij((size_t)nK * nok * nok * 8);
     for (size_t blk = 0; blk < blocks.size(); ++blk) {
@@ -444,6 +448,9 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
         transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CvKT.as<double>() + (size_t)a0 * nao, nac,
                        CvKT.as<double>(), nvk, Tab.as<double>());
         metric_apply_inplace(Linv.as<double>(), nks, Tab.as<double>(), cols, tmp, s);
+        // chunk element (p, a, a0 + a) is Bx^P_aa of window virtual a0 + a
+        gather_strided(Tab.as<double>() + a0, nks, nac, (int64_t)nac * nvk, nvk + 1,
+                       Baa.as<double>() + (size_t)blk * nks * nvk + a0, nvk, s);
         if (bf) row_absmax(Tab.as<double>(), nks, cols, cols, mxab.as<double>() + blk * nks, a0 > 0, s);
         // rows (p, a) of the chunk -> stored rows (blk * nks + p) * nvk + a0 + a
         store_block(Tab.get(), DType::F64, nvk, nac,
@@ -453,6 +460,24 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       RISP_HIP(hipStreamSynchronize(s));
     }
     tmp.release();
+    {
+      // exchange part of the diagonal: K_ia = sum_P Bx^P_ii Bx^P_aa inside the window
+      DevBuf Bii((size_t)nK * nok * 8), Kd((size_t)nok * nvk * 8);
+      gather_strided(Bij.as<double>(), nK, nok, (int64_t)nok * nok, nok + 1, Bii.as<double>(), nok, s);
+      Gemm g = g64(nok, nvk, nK);  // Kd[i][a] = sum_P Bii[P][i] Baa[P][a]
+      g.A = Bii.get();
+      g.lda = nok;
+      g.a_kc = false;
+      g.B = Baa.get();
+      g.ldb = nvk;
+      g.b_kc = false;
+      g.C = Kd.get();
+      g.ldc = nvk;
+      gemm(g, nullptr, s);
+      scatter_sub_window(Kd.as<double>(), nok, nvk, f->occ_k.as<int>(), f->vir_k.as<int>(), nvir,
+                         f->diag64.as<double>(), s);
+      RISP_HIP(hipStreamSynchronize(s));
+    }
     DevBuf sij, sab;
     if (bf) {
       slice_scales(Bij.as<double>(), nK, (int64_t)nok * nok, prm->bf16_scale != 0, sij, s);
@@ -486,6 +511,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   f->de64.alloc((size_t)nocc * nvir * 8);
   f->de32.alloc((size_t)nocc * nvir * 4);
   orbital_gaps(E.as<double>(), nocc, nvir, f->de64.as<double>(), f->de32.as<float>(), s);
+  add_inplace(f->diag64.as<double>(), f->de64.as<double>(), (int64_t)nocc * nvir, s);
   RISP_HIP(hipStreamSynchronize(s));
   if (f->j_mode == RISP_J_AO_DIRECT) {
     f->ao_sh = std::move(ao);

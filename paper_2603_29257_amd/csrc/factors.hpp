@@ -66,6 +66,9 @@ struct risp_factors {
   risp::DevBuf scale_ia, scale_ia2, scale_k;  // BF16 power-of-two scales (s_P, s_P^2, s_ij s_ab)
   risp::DevBuf occ_k, vir_k, pos_o, pos_v; // window index sets and inverse maps
   risp::DevBuf de64, de32;                 // e_a - e_i
+  // FP64 diagonal of A from the FP64 factors (Davidson guess and preconditioner): e_a - e_i
+  // + 2 sum_P B_ia^2 - [window] sum_P Bx_ii Bx_aa (no Coulomb part on the AO route)
+  risp::DevBuf diag64;
   // sigma workspaces, sized for ws_m trial vectors
   int ws_m = 0;
   int ws_csz = 0;  // bytes per element of the compute type the workspaces were sized for

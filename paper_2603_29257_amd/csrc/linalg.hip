@@ -410,6 +410,72 @@ void orbital_gaps(const double* e, int nocc, int nvir, double* de64, float* de32
   RISP_LAUNCHED();
 }
 
+// out[c] += alpha sum_r T[r][c]^2 (threads over columns, rows in a loop: coalesced rows)
+__global__ void k_col_sumsq(const double* __restrict__ T, int rows, int64_t cols, int64_t ld, double alpha,
+                            double* __restrict__ out) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < cols; c += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int r = 0; r < rows; ++r) {
+      const double v = T[(int64_t)r * ld + c];
+      acc += v * v;
+    }
+    out[c] += alpha * acc;
+  }
+}
+
+void col_sumsq(const double* T, int rows, int64_t cols, int64_t ld, double alpha, double* out, hipStream_t s) {
+  if (cols <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(cols, 256), 1 << 16);
+  k_col_sumsq<<<grid, 256, 0, s>>>(T, rows, cols, ld, alpha, out);
+  RISP_LAUNCHED();
+}
+
+__global__ void k_gather_strided(const double* __restrict__ src, int np, int nt, int64_t sp, int64_t st,
+                                 double* __restrict__ out, int64_t ldo) {
+  const int64_t n = (int64_t)np * nt;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = x / nt, t = x % nt;
+    out[p * ldo + t] = src[p * sp + t * st];
+  }
+}
+
+void gather_strided(const double* src, int np, int nt, int64_t sp, int64_t st, double* out, int64_t ldo,
+                    hipStream_t s) {
+  if ((int64_t)np * nt <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div((int64_t)np * nt, 256), 1 << 16);
+  k_gather_strided<<<grid, 256, 0, s>>>(src, np, nt, sp, st, out, ldo);
+  RISP_LAUNCHED();
+}
+
+__global__ void k_scatter_sub_window(const double* __restrict__ K, int nok, int nvk, const int* __restrict__ occ,
+                                     const int* __restrict__ vir, int nvir, double* __restrict__ diag) {
+  const int64_t n = (int64_t)nok * nvk;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(x / nvk), a = (int)(x % nvk);
+    diag[(int64_t)occ[i] * nvir + vir[a]] -= K[x];
+  }
+}
+
+void scatter_sub_window(const double* K, int nok, int nvk, const int* occ, const int* vir, int nvir, double* diag,
+                        hipStream_t s) {
+  if ((int64_t)nok * nvk <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div((int64_t)nok * nvk, 256), 1 << 16);
+  k_scatter_sub_window<<<grid, 256, 0, s>>>(K, nok, nvk, occ, vir, nvir, diag);
+  RISP_LAUNCHED();
+}
+
+__global__ void k_add_inplace(double* __restrict__ y, const double* __restrict__ x, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    y[t] += x[t];
+}
+
+void add_inplace(double* y, const double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, 256), 1 << 16);
+  k_add_inplace<<<grid, 256, 0, s>>>(y, x, n);
+  RISP_LAUNCHED();
+}
+
 __global__ void k_fill_neg(int* p, int n) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = -1;

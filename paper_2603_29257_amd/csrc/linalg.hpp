@@ -50,6 +50,15 @@ void permute_pij_ipj(const void* T, int nP, int ni, int nj, size_t esz, void* ou
 // de[i][a] = e[nocc + a] - e[i] (FP64 and FP32 copies)
 void orbital_gaps(const double* e, int nocc, int nvir, double* de64, float* de32, hipStream_t s);
 
+// pieces of the diagonal of A: out[c] += alpha sum_r T[r][c]^2 over rows of stride ld;
+// out[p][t] (row stride ldo) = src[p sp + t st]; diag[occ[i] nvir + vir[a]] -= K[i][a]; y += x
+void col_sumsq(const double* T, int rows, int64_t cols, int64_t ld, double alpha, double* out, hipStream_t s);
+void gather_strided(const double* src, int np, int nt, int64_t sp, int64_t st, double* out, int64_t ldo,
+                    hipStream_t s);
+void scatter_sub_window(const double* K, int nok, int nvk, const int* occ, const int* vir, int nvir, double* diag,
+                        hipStream_t s);
+void add_inplace(double* y, const double* x, int64_t n, hipStream_t s);
+
 // window position maps: pos[k] = index of k in idx[0..n) or -1 (length len)
 void window_positions(const int* idx, int n, int len, int* pos, hipStream_t s);
 

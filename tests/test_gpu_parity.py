@@ -173,13 +173,33 @@ def test_factors_fp32_and_bf16_storage(ctx, mol0, oracle0):
     F.free()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_diagonal_of_A(ctx, mol0, oracle0, prec):
+    # FP64 diagonal from the FP64 factors in every storage precision (guess and preconditioner)
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
+    got = F.tensor("diag_a").cpu().numpy()
+    ref = R.diag_A(oracle0)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _print(f"diag(A) {prec} max rel err {err:.3e}")
+    assert err <= 1e-9
+    F.free()
+    # the AO route leaves the Coulomb part out
+    F = _gpu_factors(ctx, mol0, precision=P.FP64, j_mode=P.J_AO_DIRECT)
+    got = F.tensor("diag_a").cpu().numpy()
+    Bf = oracle0.B_ia
+    ref_ao = ref - 2.0 * np.einsum("Pia,Pia->ia", Bf, Bf)
+    assert np.abs(got - ref_ao).max() <= 1e-9 * np.abs(ref_ao).max()
+    F.free()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_factors_chunked_build_identical(ctx, mol0, prec):
     # tiny build chunks (one occupied / window-virtual orbital per chunk) give the same stored factors
     import paper_2603_29257_amd as P
     F1 = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
     F2 = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec], build_chunk_kib=16)
-    for name in ("t_ia", "t_ij", "t_ab") + (("scale_ia", "scale_k") if prec == "bf16" else ()):
+    for name in ("t_ia", "t_ij", "t_ab", "diag_a") + (("scale_ia", "scale_k") if prec == "bf16" else ()):
         a = F1.tensor(name, padded=True).double().cpu().numpy()
         b = F2.tensor(name, padded=True).double().cpu().numpy()
         assert np.array_equal(a, b), name

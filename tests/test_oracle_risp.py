@@ -201,6 +201,13 @@ def test_coulomb_ao_route_symmetric_psd_and_linear(tiny):
     assert np.all(R.coulomb_ao(tiny, np.zeros_like(X[:1]), prm) == 0.0)
 
 
+def test_diag_A_equals_dense_diagonal(tiny):
+    for prm in (R.Params(window_ev=25.0), R.Params(rsh_mode="split")):
+        F = R.build_factors(tiny, prm)
+        ref = np.diag(R.dense_A(F)).reshape(F.nocc, F.nvir)
+        assert np.abs(R.diag_A(F) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 def test_window_sets_by_hand():
     e = np.array([-2.0, -40.0 / H2EV, -39.0 / H2EV, -0.3, 0.1, 1.0, 40.0 / H2EV, 1.5, 3.0])
     occ, vir = R.window_sets(e, 4, 40.0)
