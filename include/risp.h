@@ -127,8 +127,11 @@ typedef struct {
 } risp_dav_opts;
 
 /* risp_dav_opts.flags: RISP_DAV_VERBOSE prints one line per iteration (stage, iteration, subspace
- * size, largest residual over the requested states) to stderr. */
-enum { RISP_DAV_VERBOSE = 1 };
+ * size, largest residual over the requested states) to stderr. RISP_DAV_SPILL keeps the subspace
+ * vectors and their products (2 (max_space + block) nocc nvir elements) in pinned host memory that
+ * the kernels read and write over the host link, for subspaces that do not fit next to the factors
+ * (same arithmetic, same results; slower subspace steps). */
+enum { RISP_DAV_VERBOSE = 1, RISP_DAV_SPILL = 2 };
 
 typedef struct {
   int32_t iters, restarts, sigma_vectors, converged; /* main stage (BF16 stage for BF16 factors) */

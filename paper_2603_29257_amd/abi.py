@@ -76,6 +76,7 @@ class PhaseStatC(C.Structure):
 
 
 DAV_VERBOSE = 1  # risp_dav_opts.flags: one stderr line per Davidson iteration
+DAV_SPILL = 2  # risp_dav_opts.flags: subspace vectors and products in pinned host memory
 
 PHASES = ("coulomb_y", "coulomb_j", "exchange_m", "exchange_k", "other")
 
@@ -420,9 +421,9 @@ class Context:
         _check(_LIB.risp_serve_config(self.handle, C.byref(o)))
 
     def submit(self, sys: System, prm: Params, nstates, tol=1e-5, block=0, max_space=0, max_iter=0,
-               correction_pass=True, correction_steps=0, bf16_tol=0.0, ncorr=0, correction_ncorr=0):
+               correction_pass=True, correction_steps=0, bf16_tol=0.0, ncorr=0, correction_ncorr=0, spill=False):
         o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
-                     0, 0, None, ncorr, correction_ncorr)
+                     0, DAV_SPILL if spill else 0, None, ncorr, correction_ncorr)
         p = prm.c()
         jid = C.c_uint64()
         _check(_LIB.risp_submit(self.handle, C.byref(sys.c), C.byref(p), C.byref(o), C.byref(jid)))
@@ -454,7 +455,7 @@ class Context:
 
     def davidson(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, correction_pass=True,
                  x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0, verbose=False,
-                 ncorr=0, correction_ncorr=0):
+                 ncorr=0, correction_ncorr=0, spill=False):
         ov = F.nocc * F.nvir
         e = np.zeros(nstates)
         vec = np.zeros((nstates, ov), np.float32) if want_vectors else None
@@ -462,7 +463,7 @@ class Context:
         if x0 is not None:
             x0a = np.ascontiguousarray(x0, dtype=np.float32).reshape(-1, ov)
         o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
-                     0 if x0a is None else x0a.shape[0], DAV_VERBOSE if verbose else 0,
+                     0 if x0a is None else x0a.shape[0], (DAV_VERBOSE if verbose else 0) | (DAV_SPILL if spill else 0),
                      None if x0a is None else _ptr(x0a, C.c_float), ncorr, correction_ncorr)
         info = DavInfoC()
         import torch

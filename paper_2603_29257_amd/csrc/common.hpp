@@ -38,7 +38,7 @@ void set_last_error(const std::string& msg);
 // Kernel launch error check (does not synchronise).
 #define RISP_LAUNCHED() RISP_HIP(hipGetLastError())
 
-// Owning device allocation.
+// Owning device allocation (or pinned host allocation, see alloc_pinned).
 class DevBuf {
  public:
   DevBuf() = default;
@@ -46,11 +46,26 @@ class DevBuf {
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr; o.n_ = 0; }
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_), host_(o.host_) { o.p_ = nullptr; o.n_ = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; o.p_ = nullptr; o.n_ = 0; }
+    if (this != &o) { release(); p_ = o.p_; n_ = o.n_; host_ = o.host_; o.p_ = nullptr; o.n_ = 0; }
     return *this;
   }
+  // pinned host memory mapped into the device address space (kernels read and write it over the
+  // host link)
+  void alloc_pinned(size_t bytes) {
+    release();
+    if (bytes == 0) return;
+    hipError_t e = hipHostMalloc(&p_, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p_ = nullptr;
+      (void)hipGetLastError();
+      throw Error(RISP_E_NOMEM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    n_ = bytes;
+    host_ = true;
+  }
+  bool pinned() const { return host_; }
   void alloc(size_t bytes) {
     release();
     if (bytes == 0) return;
@@ -63,9 +78,10 @@ class DevBuf {
     n_ = bytes;
   }
   void release() {
-    if (p_) (void)hipFree(p_);
+    if (p_) (void)(host_ ? hipHostFree(p_) : hipFree(p_));
     p_ = nullptr;
     n_ = 0;
+    host_ = false;
   }
   template <typename T> T* as() const { return static_cast<T*>(p_); }
   void* get() const { return p_; }
@@ -74,6 +90,7 @@ class DevBuf {
  private:
   void* p_ = nullptr;
   size_t n_ = 0;
+  bool host_ = false;
 };
 
 template <typename T>

@@ -202,8 +202,13 @@ DavidsonRun::DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s) : 
   ld_ = cap_;
   max_iter_ = o.max_iter > 0 ? o.max_iter : 200;
   const int64_t ov = ov_;
-  V_.alloc((size_t)cap_ * ov * vsz_);
-  W_.alloc((size_t)cap_ * ov * vsz_);
+  if (o.spill) {
+    V_.alloc_pinned((size_t)cap_ * ov * vsz_);
+    W_.alloc_pinned((size_t)cap_ * ov * vsz_);
+  } else {
+    V_.alloc((size_t)cap_ * ov * vsz_);
+    W_.alloc((size_t)cap_ * ov * vsz_);
+  }
   H_.alloc((size_t)ld_ * ld_ * 8);
   Hw_.alloc((size_t)ld_ * ld_ * 8);
   Zs_.alloc((size_t)ld_ * ld_ * 8);
@@ -526,8 +531,8 @@ void DavidsonRun::thick_restart(int keep) {
     g.ldc = ov;
     gemm(g, nullptr, s_);
   }
-  RISP_HIP(hipMemcpyAsync(V_.get(), Rv_.get(), bytes, hipMemcpyDeviceToDevice, s_));
-  RISP_HIP(hipMemcpyAsync(W_.get(), Rw_.get(), bytes, hipMemcpyDeviceToDevice, s_));
+  RISP_HIP(hipMemcpyAsync(V_.get(), Rv_.get(), bytes, hipMemcpyDefault, s_));
+  RISP_HIP(hipMemcpyAsync(W_.get(), Rw_.get(), bytes, hipMemcpyDefault, s_));
   k_diag_H<<<ceil_div((int64_t)keep * keep, 256), 256, 0, s_>>>(H_.as<double>(), ld_, keep, theta_.as<double>());
   RISP_LAUNCHED();
   nsub_ = keep;

@@ -33,6 +33,7 @@ struct DavOptions {
   double stall_below = 1e300;
   const char* log_tag = nullptr;  // print one line per iteration to stderr under this tag
   int max_corr = 0;  // corrections only for the lowest max_corr Ritz pairs (0: all `block`)
+  bool spill = false;  // subspace vectors V and products W in pinned host memory
 };
 
 struct DavResult {

@@ -127,8 +127,9 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t mt = std::min<int64_t>(std::max<int64_t>(nK, 1) * blk_ov * csz, (4ll << 30) + blk_ov * csz);
   const int64_t sig = mt + blk_ov * csz + blk_ov * acc + std::max(1024 * nJ * block * acc, 4 * blk_ov * acc) +
                       block * ov * 2 + nJ * block * acc + 64 * nJ * 2;
-  const int64_t dav = 2 * cap * ov * vsz + 4 * block * ov * 8 + 4 * block * ov * vsz + 512 * cap * block * 8 +
-                      4 * cap * cap * 8;
+  const bool spill = opts && (opts->flags & RISP_DAV_SPILL);
+  const int64_t dav = (spill ? 0 : 2 * cap * ov * vsz) + 4 * block * ov * 8 + 4 * block * ov * vsz +
+                      512 * cap * block * 8 + 4 * cap * cap * 8;
   return store + std::max(build, sig + dav) + (64ll << 20);
 }
 
@@ -149,6 +150,7 @@ void Server::admit(Job& j) {
   o.max_iter = j.opts.max_iter > 0 ? j.opts.max_iter : 200;
   o.tol = j.opts.tol;
   o.max_corr = j.opts.ncorr > 0 ? j.opts.ncorr : j.opts.nstates;
+  o.spill = (j.opts.flags & RISP_DAV_SPILL) != 0;
   if (j.prm.precision == RISP_BF16) {
     if (j.opts.correction_pass) o.tol = std::max(o.tol, j.opts.bf16_tol > 0.0 ? j.opts.bf16_tol : 1e-4);
     o.stall_iters = 4;
@@ -336,6 +338,7 @@ void Server::loop() {
             oc.nstates = j.opts.nstates;
             oc.block = j.opts.block;
             oc.max_corr = j.opts.correction_ncorr > 0 ? j.opts.correction_ncorr : j.opts.nstates;
+            oc.spill = (j.opts.flags & RISP_DAV_SPILL) != 0;
             oc.max_space = j.opts.max_space;
             oc.tol = j.opts.tol;
             oc.x0_dev = j.main_res.X.as<double>();

@@ -349,6 +349,18 @@ def test_ao_route_rejected_by_serving(ctx, mol0):
         ctx.submit(P.System(mol0), _params(j_mode=P.J_AO_DIRECT), 3)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_davidson_spilled_subspace_identical(ctx, mol0, prec):
+    # the subspace in pinned host memory runs the same kernels on the same values
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
+    e1, v1, i1 = ctx.davidson(F, 5, tol=1e-5, max_space=40)
+    e2, v2, i2 = ctx.davidson(F, 5, tol=1e-5, max_space=40, spill=True)
+    assert i1.restarts > 0 and i1.iters == i2.iters
+    assert np.array_equal(e1, e2) and np.array_equal(v1, v2)
+    F.free()
+
+
 def test_errors_are_reported(ctx, mol0):
     import paper_2603_29257_amd as P
     F = _gpu_factors(ctx, mol0, precision=P.FP32)
