@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true", help="time only the plain FP32 path (long workloads)")
     ap.add_argument("--verbose", action="store_true", help="one stderr line per Davidson iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-aux", type=int, default=48, help="exchange auxiliary slices in the CPU sample")
+    ap.add_argument("--cpu-sample-aux", type=int, default=144, help="exchange auxiliary slices in the CPU sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the 64-job serving stream (the default)")
     ap.add_argument("--serving", action="store_true",
                     help="also run the 64-job serving stream (off by default: its run ended in a host "

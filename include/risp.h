@@ -101,7 +101,8 @@ typedef struct {
   int32_t bf16_scale; /* BF16 only: 1 stores each auxiliary slice scaled by a power of two */
   int32_t build_chunk_kib; /* device memory for one chunk of FP64 transformed integrals during the
                               build, in KiB; the T_ia and T_ab builds run in as many chunks of
-                              occupied / window-virtual orbitals as needed; 0 = 16 GiB */
+                              occupied / window-virtual orbitals as needed; 0 = a quarter of the
+                              free device memory, between 1 and 64 GiB */
   int32_t j_mode;     /* RISP_J_*: how the Coulomb term of sigma is formed */
   int32_t reserved;   /* 0 */
 } risp_params;

@@ -112,7 +112,10 @@ static Gemm g64(int M, int N, int K) {
 struct Stored {
   DevBuf main, f32;
 };
-constexpr int64_t kBuildChunk = 16ll << 30;  // default bytes of one FP64 chunk of transformed integrals
+// default bytes of one FP64 chunk of transformed integrals: a quarter of the free device memory at
+// the start of the build, between 1 and 64 GiB (fewer chunks = fewer passes over the integrals)
+constexpr int64_t kBuildChunkMin = 1ll << 30, kBuildChunkMax = 64ll << 30;
+constexpr int64_t kIntChunk = 16ll << 30;    // bytes of one chunk of dense (mu nu|P) slices in the build
 
 // T <- Linv T in place for T [n][cols] (row stride cols), through column panels of at most ~1 GiB
 static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t cols, DevBuf& tmp, hipStream_t s) {
@@ -179,9 +182,12 @@ static void transformed_3c(risp_ctx* ctx, hipStream_t s, const DevShells& ao, co
                            const DevShells& aux, const Operator& op, const double* CLT, int nl,
                            const double* CRT, int nr, double* out) {
   const int nao = ao.nfunc;
-  // auxiliary shell chunks of at most ~2 GB of FP64 integrals
+  // auxiliary shell chunks (the batch of the transform products): enough functions for ~2048 output
+  // tiles of the first product, within kIntChunk bytes of FP64 integrals
   const int64_t per_func = (int64_t)nao * nao * 8;
-  const int max_f = (int)std::max<int64_t>(3, std::min<int64_t>(256, (2ll << 30) / per_func));
+  const int64_t tiles_per_func = (int64_t)((nl + 127) / 128) * ((nao + 255) / 256);
+  const int max_f = (int)std::max<int64_t>(
+      3, std::min<int64_t>({256, kIntChunk / per_func, (2048 + tiles_per_func - 1) / tiles_per_func}));
   std::vector<int> l(aux.n);
   RISP_HIP(hipMemcpyAsync(l.data(), aux.l.get(), aux.n * sizeof(int), hipMemcpyDeviceToHost, s));
   RISP_HIP(hipStreamSynchronize(s));
@@ -312,7 +318,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   gather_transpose(C.as<double>(), nmo, nao, nullptr, nocc, nvir, CvT.as<double>(), s);
 
   // ---- Coulomb factor T_ia ----
-  // Built in chunks of occupied orbitals so the FP64 intermediate stays within kBuildChunk bytes
+  // Built in chunks of occupied orbitals so the FP64 intermediate stays within chunk_bytes
   // (one chunk up to a few hundred atoms): transformed integrals (Q|ia), the metric applied in place,
   // then stored rows. BF16 factors go through their FP32 copy: the per-slice scales need the maximum
   // over every chunk, and the BF16 rows are written from the FP32 copy at the end.
@@ -321,7 +327,12 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   f->diag64.alloc((size_t)std::max<int64_t>((int64_t)nocc * nvir, 1) * 8);
   fill_zero(f->diag64.get(), f->diag64.bytes(), s);
   RISP_CHECK(prm->build_chunk_kib >= 0, RISP_E_ARG, "build_chunk_kib must be non-negative");
-  const int64_t chunk_bytes = prm->build_chunk_kib > 0 ? ((int64_t)prm->build_chunk_kib << 10) : kBuildChunk;
+  int64_t chunk_bytes = (int64_t)prm->build_chunk_kib << 10;
+  if (chunk_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    RISP_HIP(hipMemGetInfo(&fr, &tot));
+    chunk_bytes = std::max(kBuildChunkMin, std::min(kBuildChunkMax, (int64_t)(fr / 4)));
+  }
   const size_t dsz = dtype_size(tdst);
   if (f->j_mode == RISP_J_AO_DIRECT) {
     // no stored T_ia: keep the metric factor and plan the auxiliary chunks of the per-sigma integral
@@ -362,7 +373,9 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     dst.alloc((size_t)std::max<int64_t>((int64_t)nJ * f->ld_ia, 1) * dsz);
     fill_zero(dst.get(), dst.bytes(), s);  // zero padding columns
     DevBuf mx((size_t)std::max(nJ, 1) * 8), tmp;
-    const int64_t ni = std::max<int64_t>(1, std::min<int64_t>(nocc, chunk_bytes / ((int64_t)nJ * std::max(nvir, 1) * 8)));
+    // occupied orbitals per chunk: a multiple of 128 (the transforms' row tile) when more than one chunk
+    int64_t ni = std::max<int64_t>(1, std::min<int64_t>(nocc, chunk_bytes / ((int64_t)nJ * std::max(nvir, 1) * 8)));
+    if (ni < nocc && ni >= 128) ni = ni / 128 * 128;
     DevBuf Tt((size_t)nJ * ni * std::max(nvir, 1) * 8);
     for (int i0 = 0; i0 < nocc; i0 += (int)ni) {
       const int nic = (int)std::min<int64_t>(ni, nocc - i0);
@@ -428,7 +441,8 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     fill_zero(dab.get(), dab.bytes(), s);
     DevBuf mxab((size_t)std::max(nK, 1) * 8), tmp;
     DevBuf Baa((size_t)nK * nvk * 8);  // Bx^P_aa, for the diagonal of A
-    const int64_t na = std::max<int64_t>(1, std::min<int64_t>(nvk, chunk_bytes / ((int64_t)nks * nvk * 8)));
+    int64_t na = std::max<int64_t>(1, std::min<int64_t>(nvk, chunk_bytes / ((int64_t)nks * nvk * 8)));
+    if (na < nvk && na >= 128) na = na / 128 * 128;
     DevBuf Bij((size_t)nK * nok * nok * 8);
     for (size_t blk = 0; blk < blocks.size(); ++blk) {
       DevBuf Linv;

@@ -70,12 +70,9 @@ template <> __device__ __forceinline__ f16v mfma_chunk<uint16_t>(uint4 a, uint4 
   __builtin_memcpy(&bv, &b, 16);
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
 }
-template <> __device__ __forceinline__ f16v mfma_chunk<float>(uint4 a, uint4 b, f16v c) {
-  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
-  return c;
+
+__device__ __forceinline__ float chunk_elt(uint4 v, int e) {
+  return __uint_as_float(e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)));
 }
 
 template <typename TE, int TI, typename TO>
@@ -165,10 +162,23 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
       for (int i = 0; i < TI; ++i) a[i] = *reinterpret_cast<const uint4*>(buf + a_off + i * 32 * ROWB + chunk);
 #pragma unroll
       for (int j = 0; j < TJ; ++j) bb[j] = *reinterpret_cast<const uint4*>(buf + b_off + j * 32 * ROWB + chunk);
+      if constexpr (sizeof(TE) == 4) {
+        // the four MFMAs of each chunk in turn over all accumulators: consecutive MFMAs never share
+        // an accumulator (each accumulator still sums its k values in the same order)
 #pragma unroll
-      for (int i = 0; i < TI; ++i)
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = mfma_chunk<TE>(a[i], bb[j], acc[i][j]);
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(chunk_elt(a[i], e), chunk_elt(bb[j], e), acc[i][j],
+                                                               0, 0, 0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) acc[i][j] = mfma_chunk<TE>(a[i], bb[j], acc[i][j]);
+      }
     }
     if (kt + 1 < nk) sstore((kt + 1) & 1);  // that stage was last read before the previous barrier
     if (kt + 2 < nk) gload(kt + 2);
@@ -309,13 +319,15 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt64(Gemm g, int tiles_m, int ti
       for (int i = 0; i < FM; ++i) a[i] = *reinterpret_cast<const double2*>(buf + a_off + i * 16 * ROWB + chunk);
 #pragma unroll
       for (int j = 0; j < FN; ++j) bb[j] = *reinterpret_cast<const double2*>(buf + b_off + j * 16 * ROWB + chunk);
+      // all first-k MFMAs, then all second-k ones: consecutive MFMAs use different accumulators
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, bb[j].x, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, bb[j].y, acc[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, bb[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, bb[j].y, acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) sstore((kt + 1) & 1);
     if (kt + 2 < nk) gload(kt + 2);

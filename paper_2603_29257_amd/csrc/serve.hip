@@ -111,7 +111,7 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t store = esz * (nJ * ov + nK * (nocc * nocc + nvir * nvir)) +
                         (prm->precision == RISP_BF16 ? 4 * (nJ * ov + nK * (nocc * nocc + nvir * nvir)) : 0);
   const int64_t per_func = nao * nao * 8;
-  const int64_t max_f = std::max<int64_t>(3, std::min<int64_t>(256, (2ll << 30) / std::max<int64_t>(per_func, 1)));
+  const int64_t max_f = std::max<int64_t>(3, std::min<int64_t>(256, (16ll << 30) / std::max<int64_t>(per_func, 1)));
   const int64_t build = 2 * nJ * ov * 8 + max_f * per_func + max_f * nocc * nao * 8 + 2 * nJ * nJ * 8 +
                         nK * (nocc * nocc + nvir * nvir) * 16 + nao * sys->nmo * 8 * 2;
   const int nstates = opts ? opts->nstates : 15;
