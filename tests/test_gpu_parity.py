@@ -294,6 +294,38 @@ def test_davidson_restart_same_answer(ctx, mol0, oracle0):
     F.free()
 
 
+# method variants: readings of the exchange operator and window, auxiliary-basis choice
+_VARIANTS = {
+    "rsh_split": (dict(rsh_mode=1), dict(rsh_mode="split")),
+    "window_frontier": (dict(window_mode=1), dict(window_mode="frontier")),
+    "window_10ev": (dict(window_ev=10.0), dict(window_ev=10.0)),
+    "window_0ev": (dict(window_ev=0.0), dict(window_ev=0.0)),
+    "h_in_aux": (dict(h_in_aux=True), dict(h_in_aux=True)),
+    "global_hybrid": (dict(beta=0.0), dict(beta=0.0)),
+    "no_exchange": (dict(c_x=0.0, beta=0.0), dict(c_x=0.0, beta=0.0)),
+}
+
+
+@pytest.mark.parametrize("variant", sorted(_VARIANTS))
+def test_sigma_method_variants_fp64(ctx, mol0, variant):
+    import paper_2603_29257_amd as P
+    gp, op = _VARIANTS[variant]
+    ref_f = R.build_factors(mol0, R.Params(**op))
+    F = _gpu_factors(ctx, mol0, precision=P.FP64, **gp)
+    assert F.naux_j == ref_f.B_ia.shape[0]
+    assert F.nocc_k == len(ref_f.occK) and F.nvir_k == len(ref_f.virK)
+    # an empty window keeps no exchange factors on the device
+    assert F.naux_k == (ref_f.Bx_ij.shape[0] if F.nocc_k and F.nvir_k else 0)
+    X = synth.random_trial_vectors(4, F.nocc, F.nvir, 23)
+    ref = R.sigma(ref_f, X)
+    got = ctx.sigma(F, torch.tensor(X, dtype=torch.float64, device=ctx.device)).cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    dg = np.abs(F.tensor("diag_a").cpu().numpy() - R.diag_A(ref_f)).max() / np.abs(R.diag_A(ref_f)).max()
+    _print(f"sigma FP64 {variant}: naux_k {F.naux_k} window {F.nocc_k}x{F.nvir_k} max rel err {err:.3e}, diag {dg:.3e}")
+    assert err <= 1e-9 and dg <= 1e-9
+    F.free()
+
+
 # ---------------------------------------------------------------------------------------------
 # Coulomb term by the AO-density route (no stored T_ia; integrals regenerated per sigma block)
 # ---------------------------------------------------------------------------------------------
