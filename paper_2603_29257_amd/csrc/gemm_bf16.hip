@@ -5,8 +5,9 @@
 // BM = 64 * TI (128, 192 or 256); each wave owns a (BM/2) x 64 sub-tile of TI x 2 32x32 MFMA
 // accumulators. K advances in slices of 128 bytes per row (64 BF16 or 32 FP32 values) through two
 // LDS stages: while the MFMAs consume one stage, the next slice (already in registers) is written
-// to the other stage and the slice after it is requested from memory, so one barrier per slice
-// suffices; with two waves per SIMD, one wave's memory phase overlaps the other's MFMAs. LDS rows
+// to the other stage halfway through the slice's MFMAs and the slice after it is then requested
+// from memory, so one barrier per slice suffices; with two waves per SIMD, one wave's memory phase
+// overlaps the other's MFMAs. LDS rows
 // are 128 bytes with the 16-byte chunks XOR-swizzled by (row / 2) mod 8, which makes both the
 // 16-byte fragment reads and the row-slice writes conflict-free without padding. Blocks are
 // renumbered so that consecutive tiles land on the same XCD (the dispatcher deals workgroups
@@ -179,9 +180,13 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
 #pragma unroll
           for (int j = 0; j < TJ; ++j) acc[i][j] = mfma_chunk<TE>(a[i], bb[j], acc[i][j]);
       }
+      if (ks == 1) {
+        // the next slice goes to the other stage (last read before the previous barrier) while this
+        // slice's remaining MFMAs run, then the slice after it is requested into the freed registers
+        if (kt + 1 < nk) sstore((kt + 1) & 1);
+        if (kt + 2 < nk) gload(kt + 2);
+      }
     }
-    if (kt + 1 < nk) sstore((kt + 1) & 1);  // that stage was last read before the previous barrier
-    if (kt + 2 < nk) gload(kt + 2);
     __syncthreads();
   }
 
@@ -328,9 +333,11 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt64(Gemm g, int tiles_m, int ti
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, bb[j].y, acc[i][j], 0, 0, 0);
+      if (st == 0) {
+        if (kt + 1 < nk) sstore((kt + 1) & 1);
+        if (kt + 2 < nk) gload(kt + 2);
+      }
     }
-    if (kt + 1 < nk) sstore((kt + 1) & 1);
-    if (kt + 2 < nk) gload(kt + 2);
     __syncthreads();
   }
 
