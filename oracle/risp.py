@@ -324,13 +324,14 @@ class DavidsonResult:
     resid: list
 
 
-def davidson(F: Factors, nstates, tol=1e-6, block=None, max_space=None, max_iter=200, sigma_fn=None):
+def davidson(F: Factors, nstates, tol=1e-6, block=None, max_space=None, max_iter=200, sigma_fn=None, diag=None,
+             verbose=False):
     """Block Davidson for the lowest eigenpairs of A (FP64).
 
-    Guess: unit vectors at the lowest e_a - e_i (ties by (i, a)). Each iteration: Rayleigh-Ritz on
-    the subspace, residuals r_k = A x_k - theta_k x_k for the lowest `block` Ritz pairs, corrections
-    t_k = r_k / (theta_k - de) (|theta - de| floored at 1e-8), two-pass classical Gram-Schmidt
-    against the subspace, drop vectors whose norm falls below 1e-6. Converged when ||r_k|| < tol for
+    Guess: unit vectors at the lowest d = e_a - e_i (or `diag`, e.g. diag_A(F)), ties by (i, a). Each
+    iteration: Rayleigh-Ritz on the subspace, residuals r_k = A x_k - theta_k x_k for the lowest
+    `block` Ritz pairs, corrections t_k = r_k / (theta_k - d) (|theta - d| floored at 1e-8), two-pass
+    classical Gram-Schmidt against the subspace, drop vectors whose norm falls below 1e-6. Converged when ||r_k|| < tol for
     k < nstates. When the subspace would exceed max_space, restart from the current Ritz vectors and
     recompute their products A V.
     """
@@ -342,7 +343,7 @@ def davidson(F: Factors, nstates, tol=1e-6, block=None, max_space=None, max_iter
     if max_space is None:
         max_space = max(8 * block, nstates + 2 * block)
     sig = sigma_fn or (lambda X: sigma(F, X.reshape(-1, o, v)).reshape(-1, n))
-    d = F.de.ravel()
+    d = (F.de if diag is None else np.asarray(diag)).ravel()
     order = np.lexsort((np.arange(n), d))[:block]  # stable: ties keep (i, a) order
     V = np.zeros((block, n))
     V[np.arange(block), order] = 1.0
@@ -360,6 +361,9 @@ def davidson(F: Factors, nstates, tol=1e-6, block=None, max_space=None, max_iter
         R = y.T @ W - theta[:, None] * Xr
         rn = np.linalg.norm(R, axis=1)
         resid.append(rn[:nstates].copy())
+        if verbose:
+            print(f"oracle davidson iteration {it}: subspace {V.shape[0]}, max residual {rn[:nstates].max():.3e}",
+                  flush=True)
         if np.all(rn[:nstates] < tol):
             return DavidsonResult(theta[:nstates], Xr[:nstates], it, restarts, nsig, True, resid)
         todo = [j for j in range(k) if rn[j] >= tol]

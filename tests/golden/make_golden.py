@@ -26,7 +26,8 @@ def main(name, nstates=15, tol=1e-7):
     t1 = time.time()
     print(f"factors {t1 - t0:.1f}s naux_j={F.B_ia.shape[0]} naux_k={F.Bx_ij.shape[0]} "
           f"noK={len(F.occK)} nvK={len(F.virK)} pairs={len(F.pairs)}", flush=True)
-    r = R.davidson(F, nstates, tol=tol, block=min(2 * nstates, 30))
+    # the diagonal of A as guess and preconditioner: same eigenpairs, far fewer iterations
+    r = R.davidson(F, nstates, tol=tol, block=min(2 * nstates, 30), diag=R.diag_A(F), verbose=True)
     t2 = time.time()
     print(f"davidson {t2 - t1:.1f}s iters={r.iters} converged={r.converged}", flush=True)
     out = {
