@@ -289,8 +289,10 @@ def main():
         "dtype": mp_, "data": "synthetic",
         "config": {"workload": args.workload, "atoms": int(mol.natm), "nao": d.nao, "nocc": d.nocc, "nvir": d.nvir,
                    "naux_j": d.naux_j, "naux_k": d.naux_k, "nocc_k": d.nocc_k, "nvir_k": d.nvir_k,
-                   "npair": d.npair, "nstates": args.nstates, "block": 30, "tol": args.tol, "window_ev": 40.0,
-                   "c_x": 0.22, "beta": 0.78, "omega": 0.2},
+                   "npair": d.npair, "shell_pairs": len(mol.shells) * (len(mol.shells) + 1) // 2,
+                   "pair_survival_pct": 100.0 * d.npair / (len(mol.shells) * (len(mol.shells) + 1) // 2),
+                   "cond_S": float(mol.cond_S), "nstates": args.nstates, "block": 30, "tol": args.tol,
+                   "window_ev": 40.0, "c_x": 0.22, "beta": 0.78, "omega": 0.2},
         "time_to_15_states_s": {p: res[p]["t2s"] for p in res},
         "sigma_tflops": {p: res[p]["sigma_tflops"] for p in res},
         "sigma_tflops_fp32_correction_stage": res["bf16"]["sigma_tflops_correction"] if "bf16" in res else None,
