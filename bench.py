@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true", help="time only the plain FP32 path (long workloads)")
     ap.add_argument("--verbose", action="store_true", help="one stderr line per Davidson iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ao", action="store_true", help="skip the AO-density Coulomb route sigma block")
     ap.add_argument("--cpu-sample-aux", type=int, default=144, help="exchange auxiliary slices in the CPU sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the 64-job serving stream (the default)")
     ap.add_argument("--serving", action="store_true",
@@ -197,6 +198,28 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 5}))
 
 
+def ao_route_block(ctx, P, sysc, torch, m=30):
+    """One sigma block of m vectors with the AO-density Coulomb route (no stored T_ia; (mu nu|P)
+    regenerated twice per block; BF16 exchange), against the stored-factor route on the same input."""
+    out = {}
+    for name, jm in (("ao", P.J_AO_DIRECT), ("mo", P.J_MO)):
+        F = ctx.build_factors(sysc, P.Params(precision=P.BF16, j_mode=jm))
+        d = F.desc
+        X = torch.randn(m, d.nocc, d.nvir, device=ctx.device, dtype=torch.float32)
+        ctx.sigma(F, X)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.sigma(F, X)
+        torch.cuda.synchronize()
+        out[name] = {"sigma_block_s": time.perf_counter() - t, "factor_bytes": d.bytes}
+        F.free()
+    ov, nao = d.nocc * d.nvir, d.nao
+    # the D and back-transform products, both integral contractions and the metric (FP64)
+    out["ao_coulomb_flops"] = 4.0 * m * (ov * nao + d.nocc * nao * nao + d.naux_j * nao * nao + d.naux_j ** 2)
+    out["m"] = m
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -313,6 +336,8 @@ def main():
     if os.path.exists(gold):
         ref = np.array(json.load(open(gold))["energies_ha"])[:args.nstates]
         out["max_abs_dE_vs_oracle_ha"] = {p: float(np.max(np.abs(np.array(res[p]["energies"]) - ref))) for p in res}
+    if not args.no_ao:
+        out["ao_route"] = ao_route_block(ctx, P, sysc, torch, m=30)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mol, args.cpu_sample_aux)
     ctx.close()
