@@ -201,6 +201,9 @@ const char *risp_last_error(void);
 /* Create a context on HIP device `device`. hip_stream: a hipStream_t to order work on, or NULL for
  * a stream owned by the context. */
 risp_status risp_ctx_create(int32_t device, void *hip_stream, risp_ctx **out);
+/* Stop serving (queued jobs are dropped, running ones finish), synchronise the stream and release
+ * the context. Factor objects still alive are detached: their only valid call is then
+ * risp_factors_free. */
 risp_status risp_ctx_destroy(risp_ctx *ctx);
 
 /* Enable (1) or disable (0) sigma phase timing; reset != 0 clears the counters. If out is not
@@ -218,8 +221,10 @@ risp_status risp_select_aux(const risp_system *sys, const risp_params *prm, int3
 
 /* Exchange window (section on exchange-space truncation): indices of occupied orbitals i with
  * e_i * 27.211386245988 > -window_ev and of virtual orbitals a (0-based in the virtual space) with
- * e_a * 27.211386245988 < window_ev (RISP_WIN_ABSOLUTE), computed on the device. occ_k [nocc] and
- * vir_k [nmo - nocc] are host buffers; counts returned in *nocc_k, *nvir_k. */
+ * e_a * 27.211386245988 < window_ev (RISP_WIN_ABSOLUTE; RISP_WIN_FRONTIER keeps i with (e_LUMO - e_i) * 27.211386245988 < window_ev
+ * and a with (e_a - e_HOMO) * 27.211386245988 < window_ev), computed on the device, in
+ * ascending order. occ_k [nocc] and vir_k [nmo - nocc] are host buffers; counts returned in
+ * *nocc_k, *nvir_k. */
 risp_status risp_window(risp_ctx *ctx, int32_t nmo, int32_t nocc, const double *mo_energy,
                         double window_ev, int32_t window_mode, int32_t *occ_k, int32_t *nocc_k,
                         int32_t *vir_k, int32_t *nvir_k);
@@ -251,21 +256,25 @@ risp_status risp_int3c(risp_ctx *ctx, const risp_system *sys, int32_t naux_shell
  * eq. TDDFT-axs_approx_integral). */
 risp_status risp_build_factors(risp_ctx *ctx, const risp_system *sys, const risp_params *prm,
                                risp_factors **out);
+/* Sizes and device pointers of a factor object (valid until risp_factors_free). */
 risp_status risp_factors_query(const risp_factors *f, risp_factors_desc *out);
+/* Release a factor object (waits for its queued work); NULL is accepted. */
 risp_status risp_factors_free(risp_factors *f);
 
 /* sigma = A X for m trial vectors (eq. TDA-risp with the factors): diagonal term, Coulomb
  * 2 T_ia (T_jb^T X) and windowed exchange sum_P T_ij^P X T_ab^P. X_dev and sigma_dev are device
  * [m][nocc][nvir] arrays of doubles (dtype RISP_FP64) or floats (RISP_FP32). Stream-ordered, no
- * synchronisation. Factors stored in BF16 compute in BF16 with FP32 accumulation and take FP32
- * X / sigma. */
+ * synchronisation (except for factors built with RISP_J_AO_DIRECT, whose integral passes
+ * synchronise the stream). Factors stored in BF16 compute in BF16 with FP32 accumulation and take
+ * FP32 X / sigma. */
 risp_status risp_sigma(risp_ctx *ctx, const risp_factors *f, int32_t m, const void *X_dev,
                        void *sigma_dev, int32_t dtype);
 
 /* Lowest nstates eigenpairs of A by block Davidson (section on large-system Davidson
- * diagonalisation): sigma blocks on MFMA, FP64 subspace projection, Gram-Schmidt and Jacobi
- * eigensolver on the device, restart when the subspace reaches max_space. energies: host
- * [nstates]; vectors: host [nstates][nocc*nvir] or NULL; info may be NULL.
+ * diagonalisation): guess and preconditioner from the diagonal of A, sigma blocks on MFMA, FP64
+ * subspace projection, Gram-Schmidt and tridiagonal eigensolver on the device, thick restart when
+ * the subspace reaches max_space; BF16 factors add the FP32 correction pass (risp_dav_opts).
+ * energies: host [nstates]; vectors: host [nstates][nocc*nvir] or NULL; info may be NULL.
  * Returns RISP_E_NOTCONV (with the last Ritz pairs written) if max_iter is reached. */
 risp_status risp_davidson(risp_ctx *ctx, const risp_factors *f, const risp_dav_opts *opts,
                           double *energies, float *vectors, risp_dav_info *info);
