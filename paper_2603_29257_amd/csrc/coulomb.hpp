@@ -1,4 +1,4 @@
-// Coulomb passes of sigma for BF16 factors: skinny MFMA kernels that stream T_ia once per pass.
+// Coulomb passes of sigma for BF16 and FP32 factors: skinny MFMA kernels that stream T_ia once per pass.
 #pragma once
 
 #include "common.hpp"
@@ -20,5 +20,12 @@ void coulomb_y_bf16(const uint16_t* T, int nJ, int64_t ld, const uint16_t* Xb, i
 // sig[mm][c] = alpha * sum_P Yt[mm][P] T[P][c] for mm < m, c < ov (sig FP32 [m][ov]).
 void coulomb_j_bf16(const uint16_t* T, int nJ, int64_t ld, int64_t ov, const uint16_t* Yt, int nJp, int m, float alpha,
                     float* sig, hipStream_t s);
+
+// The same passes for FP32 factors: X [m][ld] FP32 with zero padding, Yt FP32 [32 ceil(m/32)][nJp]
+// (no scales).
+void coulomb_y_f32(const float* T, int nJ, int64_t ld, const float* X, int m, float* part, size_t part_bytes,
+                   float* Yt, int nJp, hipStream_t s);
+void coulomb_j_f32(const float* T, int nJ, int64_t ld, int64_t ov, const float* Yt, int nJp, int m, float alpha,
+                   float* sig, hipStream_t s);
 
 }  // namespace risp

@@ -584,8 +584,10 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
     split_bytes = (size_t)kMaxSplit * f->ao_max_f * mg * 8;
   } else {
     f->ws_y.alloc((size_t)f->naux_j * m * acc);
-    f->ws_ybf.alloc((size_t)kCoulombMaxM * pad_to(f->naux_j, 32) * 2 + 16);
-    f->ws_xbf.alloc((size_t)m * f->ld_ia * 2 + 16);
+    // Coulomb passes of BF16 and FP32 factors: X with the row stride of T_ia, Yt [64][nJp]
+    const size_t xe = cs >= 4 ? 4 : 2;
+    f->ws_ybf.alloc((size_t)kCoulombMaxM * pad_to(f->naux_j, 32) * xe + 16);
+    f->ws_xbf.alloc((size_t)m * f->ld_ia * xe + 16);
     split_bytes = std::max((size_t)kMaxSplit * f->naux_j * m * acc,
                            coulomb_y_workspace(f->naux_j, std::min(m, kCoulombMaxM), f->ld_ia));
   }
@@ -802,6 +804,30 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
         coulomb_j_bf16(static_cast<const uint16_t*>(Tia), nJ, ldt, ov,
                        static_cast<const uint16_t*>(f->ws_ybf.get()), nJp, mg, 2.0f,
                        static_cast<float*>(sig) + (size_t)g0 * ov, s);
+      }
+    }
+  } else if (tc == DType::F32) {
+    // FP32 copy of X with the row stride of T_ia (zero padding), then the two skinny FP32 passes
+    need(f->ws_xbf, (size_t)m * ldt * 4, "X (padded)");
+    need(f->ws_ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 4, "Yt");
+    {
+      PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0, 8.0 * m * ov);
+      store_rows_padded(X, DType::F32, ov, m, ov, f->ws_xbf.get(), DType::F32, ldt, nullptr, 1, 1, s);
+    }
+    const int nJp = (int)pad_to(nJ, 32);
+    for (int g0 = 0; g0 < m; g0 += kCoulombMaxM) {
+      const int mg = std::min(kCoulombMaxM, m - g0);
+      {
+        PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * mg,
+                      4.0 * ((double)nJ * ov + (double)mg * ov) + 4.0 * nJ * mg);
+        coulomb_y_f32(static_cast<const float*>(Tia), nJ, ldt, f->ws_xbf.as<float>() + (size_t)g0 * ldt, mg,
+                      f->ws_split.as<float>(), f->ws_split.bytes(), f->ws_ybf.as<float>(), nJp, s);
+      }
+      {
+        PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * mg,
+                      4.0 * (double)nJ * ov + 4.0 * (double)mg * ov);
+        coulomb_j_f32(static_cast<const float*>(Tia), nJ, ldt, ov, f->ws_ybf.as<float>(), nJp, mg, 2.0f,
+                      static_cast<float*>(sig) + (size_t)g0 * ov, s);
       }
     }
   } else {
