@@ -140,7 +140,8 @@ def cholesky_split(V3_mo, V2):
     L = np.linalg.cholesky(V2)
     shp = V3_mo.shape
     Bflat = sla.solve_triangular(L, V3_mo.reshape(shp[0], -1), lower=True)
-    return Bflat.reshape(shp), L
+    # C order: the solver returns Fortran order, whose reshape would be a strided view
+    return np.ascontiguousarray(Bflat).reshape(shp), L
 
 
 @dataclass
@@ -200,8 +201,8 @@ def _exchange_factors(coords, shells, auxK, prm, pair_mask, CoK, CvK):
         Tab = _transformed(coords, shells, auxK, alpha, beta, prm.omega, pair_mask, CvK, CvK)
         L = np.linalg.cholesky(V2)
         nK = V2.shape[0]
-        Bij = sla.solve_triangular(L, Tij.reshape(nK, -1), lower=True).reshape(Tij.shape)
-        Bab = sla.solve_triangular(L, Tab.reshape(nK, -1), lower=True).reshape(Tab.shape)
+        Bij = np.ascontiguousarray(sla.solve_triangular(L, Tij.reshape(nK, -1), lower=True)).reshape(Tij.shape)
+        Bab = np.ascontiguousarray(sla.solve_triangular(L, Tab.reshape(nK, -1), lower=True)).reshape(Tab.shape)
         return Bij, Bab, L
 
     noK, nvK = CoK.shape[1], CvK.shape[1]
