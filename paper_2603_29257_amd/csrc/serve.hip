@@ -108,8 +108,10 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t nblocks = (prm->rsh_mode == RISP_RSH_SPLIT && prm->c_x != 0.0 && prm->beta != 0.0) ? 2 : 1;
   const int64_t nK = (prm->c_x != 0.0 || prm->beta != 0.0) ? heavy * nblocks : 0;
   const int64_t esz = prm->precision == RISP_FP64 ? 8 : (prm->precision == RISP_FP32 ? 4 : 2);
+  // stored factors (+ FP32 copies of BF16 factors), orbital gaps and the FP64 diagonal of A
   const int64_t store = esz * (nJ * ov + nK * (nocc * nocc + nvir * nvir)) +
-                        (prm->precision == RISP_BF16 ? 4 * (nJ * ov + nK * (nocc * nocc + nvir * nvir)) : 0);
+                        (prm->precision == RISP_BF16 ? 4 * (nJ * ov + nK * (nocc * nocc + nvir * nvir)) : 0) +
+                        ov * (8 + 4 + 8);
   const int64_t per_func = nao * nao * 8;
   const int64_t max_f = std::max<int64_t>(3, std::min<int64_t>(256, (16ll << 30) / std::max<int64_t>(per_func, 1)));
   const int64_t build = 2 * nJ * ov * 8 + max_f * per_func + max_f * nocc * nao * 8 + 2 * nJ * nJ * 8 +
@@ -125,8 +127,9 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t acc = prm->precision == RISP_FP64 ? 8 : 4;
   const int64_t blk_ov = block * nocc * nvir;
   const int64_t mt = std::min<int64_t>(std::max<int64_t>(nK, 1) * blk_ov * csz, (4ll << 30) + blk_ov * csz);
+  // padded X and Yt of the skinny Coulomb passes take 4 bytes per element for FP32 products
   const int64_t sig = mt + blk_ov * csz + blk_ov * acc + std::max(1024 * nJ * block * acc, 4 * blk_ov * acc) +
-                      block * ov * 2 + nJ * block * acc + 64 * nJ * 2;
+                      block * (ov + 8) * 4 + nJ * block * acc + 64 * (nJ + 32) * 4;
   const bool spill = opts && (opts->flags & RISP_DAV_SPILL);
   const int64_t dav = (spill ? 0 : 2 * cap * ov * vsz) + 4 * block * ov * 8 + 4 * block * ov * vsz +
                       512 * cap * block * 8 + 4 * cap * cap * 8;
