@@ -271,3 +271,139 @@ def test_screening_changes_energies_negligibly():
     w1 = np.linalg.eigvalsh(A1)[:5]
     w0 = np.linalg.eigvalsh(A0)[:5]
     assert np.abs(w1 - w0).max() <= 1e-8
+
+
+def test_davidson_diag_preconditioner_matches_eigh_config0():
+    """The diagonal-of-A guess and preconditioner path (the one that wrote the 300-atom reference
+    energies) against dense eigh, with and without restarts (Davidson section: the converged
+    eigenpairs do not depend on the guess or the preconditioner; a guess that misses a low root or a
+    wrong ordering of the guess shows up as a wrong energy here)."""
+    mol = synth.make_config0()
+    F = R.build_factors(mol, R.Params())
+    A = R.dense_A(F)
+    w, U = R.lowest_eigh(A, 5)
+    d = R.diag_A(F)
+    # the diagonal differs from the plain gaps, so this path is really a different guess
+    assert np.abs(d - F.de).max() > 1e-3
+    assert not np.array_equal(np.argsort(d.ravel(), kind="stable")[:10], np.argsort(F.de.ravel(), kind="stable")[:10])
+    for max_space in (None, 30):
+        r = R.davidson(F, 5, tol=1e-7, diag=d, max_space=max_space)
+        assert r.converged
+        if max_space == 30:
+            assert r.restarts > 0
+        assert np.abs(r.energies - w).max() <= 1e-10
+        for k in range(5):
+            assert abs(abs(np.dot(r.vectors[k], U[k])) - 1.0) <= 1e-8
+            # a true eigenpair of the dense matrix
+            res = A @ r.vectors[k] - r.energies[k] * r.vectors[k]
+            assert np.linalg.norm(res) <= 1e-7
+
+
+def brute_A_split(mol, prm):
+    """A with the split reading of the range-separated exchange assembled from 4-index AO integrals:
+    c_x (mu nu|P)(P|Q)^-1(Q|kl) + beta (mu nu|erf|P)(P|erf|Q)^-1(Q|erf|kl), each block inverting its
+    own metric (eq. RSH with one RI per operator)."""
+    auxJ, auxK = R.select_aux(mol.Z, mol.aux_radius, prm.theta, prm.h_in_aux)
+    C = mol.mo_coeff
+    o = mol.nocc
+    v = C.shape[1] - o
+    e = mol.mo_energy
+    V3 = I.int3c(mol.coords, mol.shells, auxJ)
+    ao4 = np.einsum("mnP,PQ,klQ->mnkl", V3, np.linalg.inv(I.int2c(mol.coords, auxJ)), V3, optimize=True)
+    mo4 = np.einsum("mnkl,mp,nq,kr,ls->pqrs", ao4, C, C, C, C, optimize=True)
+    V3p = I.int3c(mol.coords, mol.shells, auxK)
+    V3e = I.int3c(mol.coords, mol.shells, auxK, prm.omega)
+    ao4x = (prm.c_x * np.einsum("mnP,PQ,klQ->mnkl", V3p, np.linalg.inv(I.int2c(mol.coords, auxK)), V3p, optimize=True)
+            + prm.beta * np.einsum("mnP,PQ,klQ->mnkl", V3e, np.linalg.inv(I.int2c(mol.coords, auxK, prm.omega)), V3e,
+                                   optimize=True))
+    mo4x = np.einsum("mnkl,mp,nq,kr,ls->pqrs", ao4x, C, C, C, C, optimize=True)
+    occK, virK = R.window_sets(e, o, prm.window_ev, prm.window_mode)
+    wo = np.zeros(o, bool)
+    wo[occK] = True
+    wv = np.zeros(v, bool)
+    wv[virK] = True
+    A = 2.0 * mo4[:o, o:, :o, o:].copy()
+    A[np.arange(o)[:, None], np.arange(v)[None, :], np.arange(o)[:, None], np.arange(v)[None, :]] += \
+        e[None, o:] - e[:o, None]
+    Kx = mo4x[:o, :o, o:, o:].transpose(0, 2, 1, 3)  # [i][a][j][b] = (ij|J^|ab)
+    win = wo[:, None, None, None] & wv[None, :, None, None] & wo[None, None, :, None] & wv[None, None, None, :]
+    A -= np.where(win, Kx, 0.0)
+    return A.reshape(o * v, o * v)
+
+
+def test_dense_A_split_rsh_matches_brute_force(tiny):
+    """Split reading with both parts present (c_x and beta non-zero, finite omega): each RI block in
+    its own metric. Inverting the plain metric for the erf block, or the combined metric for both,
+    changes A at order 1e-3 relative here, far above the 1e-12 bar."""
+    prm = R.Params(rsh_mode="split", window_ev=25.0, schwarz_tau=0.0)
+    assert prm.c_x != 0.0 and prm.beta != 0.0 and 0.0 < prm.omega < 10.0
+    F = R.build_factors(tiny, prm)
+    A = R.dense_A(F)
+    Ab = brute_A_split(tiny, prm)
+    assert np.abs(A - Ab).max() <= 1e-12 * np.abs(Ab).max()
+    # the erf block in the plain metric is a different matrix (so the test can tell them apart)
+    auxJ, auxK = R.select_aux(tiny.Z, tiny.aux_radius)
+    V3e = I.int3c(tiny.coords, tiny.shells, auxK, prm.omega)
+    wrong = np.einsum("mnP,PQ,klQ->mnkl", V3e, np.linalg.inv(I.int2c(tiny.coords, auxK)), V3e)
+    right = np.einsum("mnP,PQ,klQ->mnkl", V3e, np.linalg.inv(I.int2c(tiny.coords, auxK, prm.omega)), V3e)
+    assert np.abs(wrong - right).max() > 1e-6 * np.abs(right).max()
+    # and the combined reading differs from the split one at these parameters
+    Ac = R.dense_A(R.build_factors(tiny, R.Params(rsh_mode="combined", window_ev=25.0, schwarz_tau=0.0)))
+    assert np.abs(Ac - Ab).max() > 1e-6 * np.abs(Ab).max()
+
+
+def test_schwarz_keep_rule_by_hand():
+    """Keep rule of the screening (section on on-the-fly Coulomb evaluation, screened AO pairs):
+    (A >= B) is kept iff Q_AB * max_P sqrt((P|P)) >= tau with Q_AB from the four-centre diagonal and
+    the maximum over the Coulomb (s + p) auxiliary basis. tau is set to exactly the value of one
+    same-shell pair, so the list separates >= from >, drops a same-shell pair and a p-s pair, and
+    drops more than 10 % of the pairs. Dropped pairs must satisfy the Schwarz bound on the actual
+    three-centre integrals."""
+    mol = tiny_molecule()
+    sh = mol.shells
+    nsh = len(sh)
+    auxJ0, auxK = R.select_aux(mol.Z, mol.aux_radius)
+    # In the production basis s and p share an exponent and the s function has the largest (P|P),
+    # so the Coulomb and exchange maxima coincide; more diffuse p functions here make them differ, so the
+    # test can tell which basis the rule uses.
+    auxJ = [(a, l, e * (0.1 if l == 1 else 1.0), c) for (a, l, e, c) in auxJ0]
+    assert np.sqrt(np.max(np.diag(I.int2c(mol.coords, auxJ0)))) == np.sqrt(np.max(np.diag(I.int2c(mol.coords, auxK))))
+    Qab = I.schwarz_diag(mol.coords, sh)
+    qJ = float(np.sqrt(np.max(np.diag(I.int2c(mol.coords, auxJ)))))
+    qK = float(np.sqrt(np.max(np.diag(I.int2c(mol.coords, auxK)))))
+    assert qJ > qK
+    diag_vals = sorted(set(Qab[a, a] * qJ for a in range(nsh)))
+    tau = diag_vals[1]  # the second-smallest same-shell value: the smallest same-shell pairs are dropped
+
+    def by_hand(q, strict=False):
+        out = []
+        for a in range(nsh):
+            for b in range(a + 1):
+                v = Qab[a, b] * q
+                if (v > tau) if strict else (v >= tau):
+                    out.append((a, b))
+        return out
+
+    want = by_hand(qJ)
+    got, mask, ratio = R.schwarz_pairs(mol.coords, sh, auxJ, tau)
+    assert [tuple(p) for p in got.tolist()] == want
+    dropped = [(a, b) for a in range(nsh) for b in range(a + 1) if (a, b) not in set(want)]
+    npair = nsh * (nsh + 1) // 2
+    assert 0.1 * npair <= len(dropped) < npair
+    assert any(a == b for a, b in dropped)
+    assert any(sh[a][1] != sh[b][1] for a, b in dropped)  # a p-s pair
+    # plausible mistakes give different lists at this tau
+    assert by_hand(qJ, strict=True) != want          # '>' instead of '>='
+    assert by_hand(qK) != want                        # exchange (s-only) auxiliary maximum
+    assert [(a, b) for a in range(nsh) for b in range(a + 1) if Qab[a, b] >= tau] != want  # Q_AB alone
+    # every dropped pair's integrals are below tau in magnitude (Schwarz inequality)
+    V3 = I.int3c(mol.coords, sh, auxJ)
+    off, nf = I.shell_offsets(sh)
+    off = off + [nf]
+    for a, b in dropped:
+        blk = V3[off[a]:off[a + 1], off[b]:off[b + 1], :]
+        assert np.abs(blk).max() < tau
+    # the factor build screens with the Coulomb basis
+    F = R.build_factors(mol, R.Params(schwarz_tau=1e-3))
+    ref, _, _ = R.schwarz_pairs(mol.coords, sh, auxJ0, 1e-3)
+    assert np.array_equal(F.pairs, ref) and len(ref) < npair
