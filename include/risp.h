@@ -324,6 +324,11 @@ risp_status risp_poll(risp_ctx *ctx, uint64_t job_id, risp_result *out);
 
 risp_status risp_serve_stats_get(risp_ctx *ctx, risp_serve_stats *out);
 
+/* Device memory held by the library's own allocations in this process (factors, workspaces,
+ * Davidson buffers, served jobs; not the HIP runtime's internal allocations), and its high-water mark.
+ * reset_peak != 0 first sets the mark to the current value. Host outputs. Thread-safe. */
+risp_status risp_device_usage(int64_t *live_bytes, int64_t *peak_bytes, int32_t reset_peak);
+
 #ifdef __cplusplus
 }
 #endif

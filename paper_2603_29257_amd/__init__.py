@@ -6,7 +6,7 @@ loaded on first use of a name below, so the build module imports without the lib
 """
 _EXPORTS = ("BF16", "FP32", "FP64", "PRECISIONS", "RSH_COMBINED", "RSH_SPLIT", "WIN_ABSOLUTE",
             "WIN_FRONTIER", "Context", "DavInfo", "Factors", "Params", "RispError", "System", "load_library",
-            "PHASES", "job_footprint", "J_MO", "J_AO_DIRECT")
+            "PHASES", "job_footprint", "J_MO", "J_AO_DIRECT", "device_usage")
 
 
 def __getattr__(name):

@@ -28,7 +28,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 EXPORTS = ("risp_last_error", "risp_ctx_create", "risp_ctx_destroy", "risp_ctx_profile", "risp_select_aux", "risp_window",
            "risp_screen", "risp_int2c", "risp_int3c", "risp_build_factors", "risp_factors_query",
            "risp_factors_free", "risp_sigma", "risp_davidson", "risp_serve_config", "risp_job_footprint",
-           "risp_submit", "risp_poll", "risp_serve_stats_get")
+           "risp_submit", "risp_poll", "risp_serve_stats_get", "risp_device_usage")
 
 
 class RispError(RuntimeError):
@@ -133,6 +133,7 @@ def load_library(path: str = LIBPATH):
         "risp_submit": [vp, P(SystemC), P(ParamsC), P(DavOptsC), P(C.c_uint64)],
         "risp_poll": [vp, C.c_uint64, P(ResultC)],
         "risp_serve_stats_get": [vp, P(ServeStatsC)],
+        "risp_device_usage": [P(C.c_int64), P(C.c_int64), i32],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -175,6 +176,14 @@ class Params:
         return ParamsC(self.c_x, self.beta, self.omega, self.window_ev, self.theta, self.schwarz_tau,
                        self.rsh_mode, self.window_mode, self.precision, int(self.h_in_aux),
                        int(self.bf16_scale), int(self.build_chunk_kib), int(self.j_mode), 0)
+
+
+def device_usage(reset_peak=False):
+    """(live, peak) device bytes held by the library's own allocations in this process; reset_peak
+    first sets the high-water mark to the live value."""
+    live, peak = C.c_int64(), C.c_int64()
+    _check(_LIB.risp_device_usage(C.byref(live), C.byref(peak), int(bool(reset_peak))))
+    return live.value, peak.value
 
 
 class System:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -37,6 +38,20 @@ void set_last_error(const std::string& msg);
 
 // Kernel launch error check (does not synchronise).
 #define RISP_LAUNCHED() RISP_HIP(hipGetLastError())
+
+// Device bytes held by DevBuf allocations of this process and their high-water mark (pinned host
+// buffers are not counted); read through risp_device_usage.
+struct DeviceUsage {
+  std::atomic<int64_t> live{0}, peak{0};
+  void add(int64_t n) {
+    const int64_t now = live.fetch_add(n) + n;
+    int64_t p = peak.load();
+    while (now > p && !peak.compare_exchange_weak(p, now)) {
+    }
+  }
+  void sub(int64_t n) { live.fetch_sub(n); }
+};
+inline DeviceUsage g_device_usage;
 
 // Owning device allocation (or pinned host allocation, see alloc_pinned).
 class DevBuf {
@@ -76,8 +91,10 @@ class DevBuf {
       throw Error(RISP_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
     n_ = bytes;
+    g_device_usage.add((int64_t)bytes);
   }
   void release() {
+    if (p_ && !host_) g_device_usage.sub((int64_t)n_);
     if (p_) (void)(host_ ? hipHostFree(p_) : hipFree(p_));
     p_ = nullptr;
     n_ = 0;

@@ -92,9 +92,12 @@ __global__ void k_scale_rows(double* T, int nt, int64_t ov, const double* norms)
 
 // Gram-Schmidt in coefficient space on one block: given G = T T^T (nt x nt, nt <= 64), build the
 // coefficients Q = Cf T of an orthonormal basis of span(T), dropping vectors whose remaining norm is
-// below drop * (norm of the input vector). Cf is [nt][nt] (rows of kept vectors first), count out.
-// One wave: lane i holds component i of the candidate; G and the kept rows sit in LDS.
-__global__ __launch_bounds__(64) void k_block_mgs(const double* __restrict__ G, int nt, double drop,
+// below drop * ref, where ref is 1 when unit_ref (rows that had unit length before an earlier
+// projection against the subspace, so a row that the projection reduced to rounding noise is
+// dropped too) and otherwise the row's own norm sqrt(G_jj). Cf is [nt][nt] (rows of kept vectors
+// first), count out. One wave: lane i holds component i of the candidate; G and the kept rows sit
+// in LDS.
+__global__ __launch_bounds__(64) void k_block_mgs(const double* __restrict__ G, int nt, double drop, int unit_ref,
                                                   double* __restrict__ Cf, int* __restrict__ kept) {
   __shared__ double sG[64 * 64];
   __shared__ double sQ[64 * 64];
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(64) void k_block_mgs(const double* __restrict__ G, 
     double gc = 0.0;
     for (int b = 0; b < nt; ++b) gc += (lane < nt ? sG[lane * nt + b] : 0.0) * __shfl(c, b, 64);
     const double n2 = wsum(lane < nt ? c * gc : 0.0);
-    const double tj = sqrt(fmax(sG[j * nt + j], 0.0));
+    const double tj = unit_ref ? 1.0 : sqrt(fmax(sG[j * nt + j], 0.0));
     const double nn = sqrt(fmax(n2, 0.0));
     if (nn > drop * tj && nn > 0.0) {
       if (lane < nt) sQ[nk * 64 + lane] = c / nn;
@@ -187,6 +190,8 @@ DavidsonRun::DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s) : 
   fp64_ = f->precision == RISP_FP64;
   tvec_ = fp64_ ? DType::F64 : DType::F32;
   vsz_ = fp64_ ? 8 : 4;
+  // drop threshold of the Gram-Schmidt: a few times above the rounding of the stored subspace
+  drop_ = fp64_ ? 1e-6 : 1e-5;
   nstates_ = o.nstates;
   RISP_CHECK(nstates_ > 0 && nstates_ <= ov_, RISP_E_ARG, "nstates out of range");
   RISP_CHECK(o.tol > 0.0, RISP_E_ARG, "tol must be positive");
@@ -235,7 +240,7 @@ DavidsonRun::DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s) : 
   if (o.nx0 > 0 && o.x0_dev) {
     const int n0 = std::min(o.nx0, block_);
     RISP_HIP(hipMemcpyAsync(T_.get(), o.x0_dev, (size_t)n0 * ov * 8, hipMemcpyDeviceToDevice, s_));
-    const int nk = orth_block(n0);
+    const int nk = orth_block(n0, false);
     RISP_CHECK(nk > 0, RISP_E_ARG, "initial vectors are zero or dependent");
     store_T(0, nk);
     rq_ = {0, nk};
@@ -323,8 +328,10 @@ void DavidsonRun::combine_rows(const double* Cm, int ldcm, int nsub, int k, cons
   gemm(g, nullptr, s_);
 }
 
-// orthonormalise the nt FP64 rows of T within the block (coefficient-space Gram-Schmidt, twice)
-int DavidsonRun::orth_block(int nt) {
+// orthonormalise the nt FP64 rows of T within the block (coefficient-space Gram-Schmidt, twice).
+// unit_ref: the rows had unit length before they were projected off the subspace, and the drop test
+// compares with that length (first pass; the second pass sees rows of unit length anyway)
+int DavidsonRun::orth_block(int nt, bool unit_ref) {
   RISP_CHECK(nt <= 64, RISP_E_ARG, "block orthonormalisation handles at most 64 vectors");
   int nk = nt;
   for (int pass = 0; pass < 2 && nk > 0; ++pass) {
@@ -341,7 +348,8 @@ int DavidsonRun::orth_block(int nt) {
     g.ldc = nk;
     g.ksplit = std::min(kDavSplit, gemm_auto_split(g));
     gemm(g, split_.get(), s_);
-    k_block_mgs<<<1, 64, 0, s_>>>(G_.as<double>(), nk, 1e-6, Cf_.as<double>(), kept_.as<int>());
+    k_block_mgs<<<1, 64, 0, s_>>>(G_.as<double>(), nk, drop_, (unit_ref || pass > 0) ? 1 : 0, Cf_.as<double>(),
+                                  kept_.as<int>());
     RISP_LAUNCHED();
     int h = 0;
     RISP_HIP(hipMemcpyAsync(&h, kept_.get(), sizeof(int), hipMemcpyDeviceToHost, s_));
@@ -423,7 +431,7 @@ void DavidsonRun::finish(Timer& tsub) {
 // project, orthonormalise and append the nt corrections in T, then request their sigma
 void DavidsonRun::append_corrections(int nt, Timer& tsub) {
   project_out(nsub_, nt);
-  const int nk = orth_block(nt);
+  const int nk = orth_block(nt, true);
   if (nk == 0) {  // no new direction: the subspace cannot grow
     finish(tsub);
     return;

@@ -70,7 +70,7 @@ class DavidsonRun {
   void row_norms(const double* R, int k, double* out_dev);
   void combine_rows(const double* Cm, int ldcm, int nsub, int k, const void* Vsrc, double* out, double alpha,
                     double beta);
-  int orth_block(int nt);
+  int orth_block(int nt, bool unit_ref);
   void project_out(int nsub, int nt);
   void store_T(int r0, int n);
   void iterate(Timer& tsub);
@@ -88,6 +88,7 @@ class DavidsonRun {
   int nstates_ = 0, block_ = 0, max_space_ = 0, cap_ = 0, ld_ = 0, max_iter_ = 0, nblk_ = 1;
   int nsub_ = 0, best_it_ = 0;
   double best_r_ = 1e300;
+  double drop_ = 1e-6;
   State state_ = State::Init;
   Request rq_;
   DavResult res_;

@@ -475,6 +475,16 @@ risp_status risp_poll(risp_ctx* ctx, uint64_t job_id, risp_result* out) {
   });
 }
 
+risp_status risp_device_usage(int64_t* live_bytes, int64_t* peak_bytes, int32_t reset_peak) {
+  return guarded([&]() -> risp_status {
+    RISP_CHECK(live_bytes && peak_bytes, RISP_E_ARG, "NULL argument");
+    if (reset_peak) g_device_usage.peak.store(g_device_usage.live.load());
+    *live_bytes = g_device_usage.live.load();
+    *peak_bytes = g_device_usage.peak.load();
+    return RISP_OK;
+  });
+}
+
 risp_status risp_serve_stats_get(risp_ctx* ctx, risp_serve_stats* out) {
   return guarded([&]() -> risp_status {
     RISP_CHECK(ctx && out, RISP_E_ARG, "NULL argument");

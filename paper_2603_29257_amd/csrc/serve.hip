@@ -8,6 +8,7 @@
 // factors, workspaces and stream; fixed reduction orders), so its result is the same alone and in a
 // mix.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -78,6 +79,7 @@ struct Server {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<std::unique_ptr<Job>> queue;
+  // resident jobs: only the scheduler thread changes the vector, under mu (serve_stats reads its size)
   std::vector<std::unique_ptr<Job>> active;
   std::map<uint64_t, std::unique_ptr<Job>> done;
   std::set<uint64_t> inflight;  // queued or active ids (guarded by mu)
@@ -88,7 +90,7 @@ struct Server {
   bool stop = false;
   std::thread thread;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-  int64_t ticks = 0, graph_ticks = 0;
+  std::atomic<int64_t> ticks{0}, graph_ticks{0};  // written by the scheduler, read by serve_stats
 
   void loop();
   void admit(Job& j);
@@ -131,8 +133,12 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t sig = mt + blk_ov * csz + blk_ov * acc + std::max(1024 * nJ * block * acc, 4 * blk_ov * acc) +
                       block * (ov + 8) * 4 + nJ * block * acc + 64 * (nJ + 32) * 4;
   const bool spill = opts && (opts->flags & RISP_DAV_SPILL);
+  // V, W (unless spilled); Ritz vectors, residuals and two correction buffers (FP64); the thick
+  // restart's two staging copies of 2 block rows; split-K partial sums; the subspace matrices; and
+  // for BF16 jobs with a correction pass the main stage's Ritz vectors, which seed the FP32 stage
+  const bool corr = prm->precision == RISP_BF16 && opts && opts->correction_pass;
   const int64_t dav = (spill ? 0 : 2 * cap * ov * vsz) + 4 * block * ov * 8 + 4 * block * ov * vsz +
-                      512 * cap * block * 8 + 4 * cap * cap * 8;
+                      512 * cap * block * 8 + 4 * cap * cap * 8 + (corr ? block * ov * 8 : 0);
   return store + std::max(build, sig + dav) + (64ll << 20);
 }
 
@@ -305,6 +311,7 @@ void Server::loop() {
     for (auto& j : admitted) {
       try {
         admit(*j);
+        std::lock_guard<std::mutex> lk(mu);
         active.push_back(std::move(j));
       } catch (const std::exception& ex) {
         j->status = dynamic_cast<const Error*>(&ex) ? static_cast<const Error&>(ex).code : RISP_E_HIP;
@@ -320,8 +327,12 @@ void Server::loop() {
         j->status = dynamic_cast<const Error*>(&ex) ? static_cast<const Error&>(ex).code : RISP_E_HIP;
         j->message = ex.what();
       }
-      for (auto& j : active) finish(std::move(j));
-      active.clear();
+      std::vector<std::unique_ptr<Job>> failed;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        failed.swap(active);
+      }
+      for (auto& j : failed) finish(std::move(j));
       continue;
     }
     // retire finished runs; start the FP32 correction stage where it applies
@@ -347,6 +358,9 @@ void Server::loop() {
             oc.x0_dev = j.main_res.X.as<double>();
             oc.nx0 = j.main_res.krows;
             oc.max_iter = 1 + (j.opts.correction_steps > 0 ? j.opts.correction_steps : 16);
+            // the finished main-stage run goes first, so the job never holds two runs' buffers
+            // (main_res.X, already moved out of it, seeds the correction run)
+            j.run.reset();
             j.run = std::make_unique<DavidsonRun>(j.F.get(), oc, j.stream);
             j.stage = 1;
             ++it;
@@ -364,8 +378,12 @@ void Server::loop() {
         j.status = dynamic_cast<const Error*>(&ex) ? static_cast<const Error&>(ex).code : RISP_E_HIP;
         j.message = ex.what();
       }
-      std::unique_ptr<Job> fin = std::move(*it);
-      it = active.erase(it);
+      std::unique_ptr<Job> fin;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        fin = std::move(*it);
+        it = active.erase(it);
+      }
       finish(std::move(fin));
     }
   }

@@ -60,6 +60,8 @@ def test_energies_vs_oracle_300_atoms(big, prec, tol_e):
     gold = json.load(open(GOLD))
     ref = np.array(gold["energies_ha"])
     F = ctx.build_factors(sysc, P.Params(precision=P.PRECISIONS[prec]))
+    d = F.desc
+    assert (d.npair, d.nocc_k, d.nvir_k) == (gold["npair"], gold["nocc_k"], gold["nvir_k"])
     e, _, info = ctx.davidson(F, len(ref), tol=1e-5, want_vectors=False)
     err = np.abs(e - ref)
     print(f"{prec}: per-state |E - E_oracle| max {err.max():.3e} Ha, iterations {info.iters}+"

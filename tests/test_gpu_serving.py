@@ -117,3 +117,28 @@ def test_tiny_budget_queues_and_failures_are_isolated(mols):
             ctx.poll(10 ** 9, 3)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("name,prec,ns", [("chainring50", "bf16", 5), ("chainring40", "fp32", 4)])
+def test_job_peak_memory_within_footprint(mols, name, prec, ns):
+    """The admission footprint bounds what a job really holds: the library's device high-water mark
+    while one job runs (BF16 with its FP32 correction stage, whose hand-off used to hold two
+    Davidson runs at once; and FP32) stays within risp_job_footprint."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_29257_amd as P
+    ctx = P.Context(0)
+    try:
+        sysc = P.System(mols[name])
+        prm = P.Params(precision=P.PRECISIONS[prec])
+        fp = P.job_footprint(sysc, prm, nstates=ns)
+        live0, _ = P.device_usage(reset_peak=True)
+        jid = ctx.submit(sysc, prm, ns, tol=1e-5)
+        r = _wait(ctx, [jid], [ns])[jid]
+        assert r["status"] == 0, r["message"]
+        live1, peak = P.device_usage()
+        print(f"{name} {prec}: peak {peak - live0} bytes, footprint {fp}, left behind {live1 - live0}", flush=True)
+        assert peak - live0 <= fp
+        assert live1 == live0  # every job buffer was released
+    finally:
+        ctx.close()
