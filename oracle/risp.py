@@ -306,6 +306,107 @@ def sigma_ao(F: Factors, mol, X: np.ndarray, prm: Params = Params()) -> np.ndarr
     return sigma(F, X, coulomb=coulomb_ao(mol, X, prm))
 
 
+def sigma_rows_chunk(mol, prm: Params, pair_mask, kind, shell_idx, D, rows_i, rows_a):
+    """Integral work of sigma_rows for one chunk of auxiliary shells (no reduction across chunks).
+
+    kind "J": Coulomb auxiliary shells shell_idx. Returns (R [nP][m], Tq [nP][r]) with
+    R_Pm = sum_(mu nu) (mu nu|P) D_m,mu nu (D_m = C_occ X_m C_vir^T, the AO transition density, so
+    R_Pm = sum_ia (ia|P) X_m,ia) and Tq_Pr = (i_r a_r|P).
+    kind "K": exchange auxiliary shells shell_idx with the operator J^ = c_x/r + beta erf(omega r)/r.
+    Returns (Ti [nP][r][noK], Ta [nP][r][nvK]) with Ti_Prj = (i_r j|J^|P) for j in occK' and
+    Ta_Prb = (a_r b|J^|P) for b in virK'.
+    """
+    coords, shells = mol.coords, mol.shells
+    auxJ, auxK = select_aux(mol.Z, mol.aux_radius, prm.theta, prm.h_in_aux)
+    C = mol.mo_coeff
+    nocc = mol.nocc
+    Co, Cv = C[:, :nocc], C[:, nocc:]
+    if kind == "J":
+        V3 = I.int3c(coords, shells, auxJ, None, pair_mask, list(shell_idx))  # [mu][nu][P]
+        nao, nP = V3.shape[0], V3.shape[2]
+        m = D.shape[0]
+        R = V3.reshape(nao * nao, nP).T @ np.asarray(D).reshape(m, nao * nao).T  # [P][m]
+        iu, inv = np.unique(rows_i, return_inverse=True)
+        H = np.einsum("mu,mnP->unP", Co[:, iu], V3, optimize=True)  # (i nu|P)
+        Tq = np.einsum("rnP,nr->Pr", H[inv], Cv[:, rows_a], optimize=True)
+        return R, Tq
+    if kind == "K":
+        V3 = _operator_int3c(coords, shells, auxK, prm.c_x, prm.beta, prm.omega, pair_mask, list(shell_idx))
+        occK, virK = window_sets(mol.mo_energy, nocc, prm.window_ev, prm.window_mode)
+        Hi = np.einsum("mr,mnP->rnP", Co[:, rows_i], V3, optimize=True)
+        Ha = np.einsum("mr,mnP->rnP", Cv[:, rows_a], V3, optimize=True)
+        Ti = np.einsum("rnP,nj->Prj", Hi, Co[:, occK], optimize=True)
+        Ta = np.einsum("rnP,nb->Prb", Ha, Cv[:, virK], optimize=True)
+        return Ti, Ta
+    raise ValueError(kind)
+
+
+def sigma_rows_tasks(mol, prm: Params = Params(), j_chunk=4, k_chunk=8):
+    """The (kind, shell_idx) chunks that sigma_rows evaluates, Coulomb first."""
+    auxJ, auxK = select_aux(mol.Z, mol.aux_radius, prm.theta, prm.h_in_aux)
+    tasks = [("J", tuple(range(s, min(len(auxJ), s + j_chunk)))) for s in range(0, len(auxJ), j_chunk)]
+    tasks += [("K", tuple(range(s, min(len(auxK), s + k_chunk)))) for s in range(0, len(auxK), k_chunk)]
+    return tasks
+
+
+def sigma_rows(mol, X, rows, prm: Params = Params(), pair_mask=None, run_chunks=None, D=None):
+    """Selected elements of sigma = A X straight from the integrals, without storing any factor.
+
+    rows: flat indices r = i*nvir + a. Returns [m][len(rows)]. For each row (i, a):
+      sigma_m,ia = (e_a - e_i) X_m,ia + 2 sum_P B^P_ia Y^P_m - [i in occK', a in virK'] K_m,ia,
+      B = L_J^-1 (Q|ia), Y = L_J^-1 R with R_Q = sum_jb (jb|Q) X_m,jb (formed from the AO transition
+      density, as in coulomb_ao), and K_m,ia = sum_P sum_(j,b in window) Bx^P_ij X_m,jb Bx^P_ab with
+      Bx = L_K^-1 (pq|J^|Q) in the J^ metric (eq. K_mia_RSH, combined reading).
+    This is the same matrix as build_factors/sigma; only the needed rows of the factors are formed, so
+    it runs at sizes whose factors do not fit in host memory. run_chunks(tasks, D, rows_i, rows_a):
+    optional replacement of the serial loop over sigma_rows_chunk (e.g. a process pool), returning
+    the chunk results in task order; D: optional precomputed AO transition densities [m][nao][nao].
+    """
+    if prm.rsh_mode != "combined":
+        raise NotImplementedError("sigma_rows implements the combined reading of the exchange operator")
+    coords, shells = mol.coords, mol.shells
+    auxJ, auxK = select_aux(mol.Z, mol.aux_radius, prm.theta, prm.h_in_aux)
+    if pair_mask is None:
+        _, pair_mask, _ = schwarz_pairs(coords, shells, auxJ, prm.schwarz_tau)
+    C = mol.mo_coeff
+    nocc, nvir = mol.nocc, C.shape[1] - mol.nocc
+    Co, Cv = C[:, :nocc], C[:, nocc:]
+    X = np.asarray(X, dtype=np.float64)
+    m = X.shape[0]
+    rows = np.asarray(rows, dtype=np.int64)
+    ri, ra = rows // nvir, rows % nvir
+    if D is None and run_chunks is None:
+        D = np.einsum("mi,kia,na->kmn", Co, X, Cv, optimize=True)
+    tasks = sigma_rows_tasks(mol, prm)
+    if run_chunks is None:
+        res = [sigma_rows_chunk(mol, prm, pair_mask, k, idx, D, ri, ra) for k, idx in tasks]
+    else:
+        res = list(run_chunks(tasks, D, ri, ra))
+    nJt = sum(1 for t in tasks if t[0] == "J")
+    R = np.concatenate([r[0] for r in res[:nJt]], axis=0)  # [naux_J][m]
+    Tq = np.concatenate([r[1] for r in res[:nJt]], axis=0)  # [naux_J][r]
+    LJ = np.linalg.cholesky(I.int2c(coords, auxJ))
+    B = sla.solve_triangular(LJ, Tq, lower=True)
+    Y = sla.solve_triangular(LJ, R, lower=True)
+    e = mol.mo_energy
+    out = (e[nocc + ra] - e[ri])[None, :] * X.reshape(m, -1)[:, rows] + 2.0 * (Y.T @ B)
+    if (prm.c_x != 0.0 or prm.beta != 0.0) and len(auxK):
+        occK, virK = window_sets(e, nocc, prm.window_ev, prm.window_mode)
+        Ti = np.concatenate([r[0] for r in res[nJt:]], axis=0)  # [nK][r][noK]
+        Ta = np.concatenate([r[1] for r in res[nJt:]], axis=0)  # [nK][r][nvK]
+        LK = np.linalg.cholesky(_operator_int2c(coords, auxK, prm.c_x, prm.beta, prm.omega))
+        nK, nr = Ti.shape[0], Ti.shape[1]
+        Bi = sla.solve_triangular(LK, Ti.reshape(nK, -1), lower=True).reshape(Ti.shape)
+        Ba = sla.solve_triangular(LK, Ta.reshape(nK, -1), lower=True).reshape(Ta.shape)
+        Xw = X[:, occK][:, :, virK]  # [m][noK][nvK]
+        inw = np.isin(ri, occK) & np.isin(ra, virK)
+        for r in np.nonzero(inw)[0]:
+            # K_m = sum_P Bi[P, r, :] Xw_m Ba[P, r, :]
+            G = np.einsum("Pj,Pb->jb", Bi[:, r, :], Ba[:, r, :], optimize=True)
+            out[:, r] -= np.einsum("mjb,jb->m", Xw, G, optimize=True)
+    return out
+
+
 def lowest_eigh(A, n):
     w, U = np.linalg.eigh(A)
     return w[:n], U[:, :n].T

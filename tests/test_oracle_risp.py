@@ -407,3 +407,24 @@ def test_schwarz_keep_rule_by_hand():
     F = R.build_factors(mol, R.Params(schwarz_tau=1e-3))
     ref, _, _ = R.schwarz_pairs(mol.coords, sh, auxJ0, 1e-3)
     assert np.array_equal(F.pairs, ref) and len(ref) < npair
+
+
+def test_sigma_rows_equals_full_sigma():
+    """sigma_rows (rows of sigma from the integrals, no stored factor; used for the full-size sampled
+    references) equals the stored-factor sigma at the same rows, inside and outside the window, for
+    the 20-atom molecule, with the default and a 10 eV window."""
+    mol = synth.make_config0()
+    X = synth.random_trial_vectors(3, mol.nocc, mol.nvir, 7)
+    nv = mol.nvir
+    for window in (40.0, 10.0):
+        prm = R.Params(window_ev=window)
+        F = R.build_factors(mol, prm)
+        nvk = len(F.virK)
+        rows = np.array([0, 5, nvk - 1, nvk, nv - 1, 3 * nv + 90, (mol.nocc - 1) * nv + nvk - 1,
+                         mol.nocc * nv - 1])
+        want = R.sigma(F, X).reshape(3, -1)[:, rows]
+        got = R.sigma_rows(mol, X, rows, prm)
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+        # the exchange part is present (dropping it changes the in-window rows)
+        F0 = R.build_factors(mol, R.Params(window_ev=window, c_x=0.0, beta=0.0))
+        assert np.abs(R.sigma(F0, X).reshape(3, -1)[:, rows] - want).max() > 1e-4 * np.abs(want).max()
