@@ -270,6 +270,24 @@ risp_status risp_factors_free(risp_factors *f);
 risp_status risp_sigma(risp_ctx *ctx, const risp_factors *f, int32_t m, const void *X_dev,
                        void *sigma_dev, int32_t dtype);
 
+/* Bytes of the library's fixed device scratch array (one copy per device, held from the moment
+ * the library's code object is loaded on that device until the process ends). */
+#define RISP_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): risp_sigma with every workspace (padded X copy, Coulomb partial
+ * sums, window block, exchange intermediate and accumulator) taken from the fixed scratch array of
+ * RISP_SCRATCH_BYTES; it calls no hipMalloc/hipFree. Same arguments, layouts, stream and
+ * precision rules as risp_sigma; the caller owns X_dev and sigma_dev. The result equals
+ * risp_sigma's up to the summation order of the exchange accumulation (fewer auxiliary functions per
+ * chunk). Returns RISP_E_SHAPE, writing nothing, when m vectors of these factors need more scratch
+ * than the array holds (e.g. BF16 factors of a 300-atom molecule take up to about 60 vectors per
+ * call), and RISP_E_ARG for factors built with RISP_J_AO_DIRECT. Every call on a device shares that
+ * device's array and leaves its contents behind: calls that overlap on one device (two streams, two
+ * threads, two contexts) race, so serialise them. Stream-ordered, no synchronisation. */
+risp_status risp_sigma_noalloc(risp_ctx *ctx, const risp_factors *f, int32_t m, const void *X_dev,
+                               void *sigma_dev, int32_t dtype);
+
 /* Lowest nstates eigenpairs of A by block Davidson (section on large-system Davidson
  * diagonalisation): guess and preconditioner from the diagonal of A, sigma blocks on MFMA, FP64
  * subspace projection, Gram-Schmidt and tridiagonal eigensolver on the device, thick restart when

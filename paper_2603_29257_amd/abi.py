@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 EXPORTS = ("risp_last_error", "risp_ctx_create", "risp_ctx_destroy", "risp_ctx_profile", "risp_select_aux", "risp_window",
            "risp_screen", "risp_int2c", "risp_int3c", "risp_build_factors", "risp_factors_query",
-           "risp_factors_free", "risp_sigma", "risp_davidson", "risp_serve_config", "risp_job_footprint",
+           "risp_factors_free", "risp_sigma", "risp_sigma_noalloc", "risp_davidson", "risp_serve_config", "risp_job_footprint",
            "risp_submit", "risp_poll", "risp_serve_stats_get", "risp_device_usage")
 
 
@@ -127,6 +127,7 @@ def load_library(path: str = LIBPATH):
         "risp_factors_query": [vp, P(FactorsDescC)],
         "risp_factors_free": [vp],
         "risp_sigma": [vp, vp, i32, vp, vp, i32],
+        "risp_sigma_noalloc": [vp, vp, i32, vp, vp, i32],
         "risp_davidson": [vp, vp, P(DavOptsC), P(dbl), P(C.c_float), P(DavInfoC)],
         "risp_serve_config": [vp, P(ServeOptsC)],
         "risp_job_footprint": [P(SystemC), P(ParamsC), P(DavOptsC), P(C.c_int64)],
@@ -405,8 +406,11 @@ class Context:
         _check(_LIB.risp_build_factors(self.handle, C.byref(sys.c), C.byref(p), C.byref(h)))
         return Factors(self, h)
 
-    def sigma(self, F: Factors, X, out=None):
-        """sigma = A X for a device tensor X [m][nocc][nvir] (float64 for FP64 factors, else float32)."""
+    def sigma(self, F: Factors, X, out=None, noalloc=False):
+        """sigma = A X for a device tensor X [m][nocc][nvir] (float64 for FP64 factors, else float32).
+
+        noalloc: call risp_sigma_noalloc (workspaces in the library's fixed scratch array; `out`
+        should then be given, so that nothing is allocated on this path either)."""
         import torch
         want = torch.float64 if F.desc.precision == FP64 else torch.float32
         if X.dtype != want or X.device != self.device or not X.is_contiguous():
@@ -415,10 +419,13 @@ class Context:
             raise ValueError("X must have shape [m, nocc, nvir]")
         if out is None:
             out = torch.empty_like(X)
+        elif out.shape != X.shape or out.dtype != want or out.device != self.device or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor shaped and typed like X")
         cur = torch.cuda.current_stream(self.device)
         self.stream.wait_stream(cur)
-        _check(_LIB.risp_sigma(self.handle, F.handle, X.shape[0], C.c_void_p(X.data_ptr()),
-                               C.c_void_p(out.data_ptr()), FP64 if want == torch.float64 else FP32))
+        fn = _LIB.risp_sigma_noalloc if noalloc else _LIB.risp_sigma
+        _check(fn(self.handle, F.handle, X.shape[0], C.c_void_p(X.data_ptr()),
+                  C.c_void_p(out.data_ptr()), FP64 if want == torch.float64 else FP32))
         cur.wait_stream(self.stream)
         X.record_stream(self.stream)
         out.record_stream(self.stream)

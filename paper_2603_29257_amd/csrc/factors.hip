@@ -563,8 +563,8 @@ constexpr int64_t kMtBudget = 4ll << 30;      // bytes of the exchange intermedi
 static int64_t pad_to(int64_t n, int64_t q) { return (n + q - 1) / q * q; }
 
 // auxiliary functions per exchange chunk for element size c: the intermediate stays within the budget
-static int64_t mt_chunk(int64_t nK, int64_t per_p, int64_t c) {
-  return std::max<int64_t>(1, std::min<int64_t>(nK, kMtBudget / (per_p * c)));
+static int64_t mt_chunk(int64_t nK, int64_t per_p, int64_t c, int64_t budget = kMtBudget) {
+  return std::max<int64_t>(1, std::min<int64_t>(nK, budget / (per_p * c)));
 }
 
 static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
@@ -617,6 +617,25 @@ void sigma_prepare(risp_factors* f, int m, bool use_f32) {
 static void need(const DevBuf& b, size_t bytes, const char* what) {
   RISP_CHECK(b.bytes() >= bytes, RISP_E_STATE, std::string("sigma workspace too small: ") + what);
 }
+
+// Non-owning view of one sigma workspace (a DevBuf of the factor object, or a piece of a fixed
+// scratch buffer).
+struct WsView {
+  void* p = nullptr;
+  size_t n = 0;
+  void* get() const { return p; }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+  size_t bytes() const { return n; }
+};
+static void need(const WsView& b, size_t bytes, const char* what) {
+  RISP_CHECK(b.bytes() >= bytes, RISP_E_STATE, std::string("sigma workspace too small: ") + what);
+}
+// The workspaces of one sigma call and the byte budget of one exchange chunk (which fixes the
+// auxiliary functions per chunk, hence the summation order).
+struct SigmaWs {
+  WsView y, ybf, xbf, xw, mt, k, split;
+  int64_t mt_budget = kMtBudget;
+};
 
 // Coulomb term by the AO-density route (section on on-the-fly Coulomb evaluation), FP64 throughout,
 // for groups of mg trial vectors:
@@ -760,14 +779,12 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
   }
 }
 
-void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s) {
-  if (m <= 0) return;
+static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s, const SigmaWs& w) {
   const bool bf = f->precision == RISP_BF16 && !use_f32;
   const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
   const DType tv = f->precision == RISP_FP64 ? DType::F64 : DType::F32;  // X / sigma type
   const DType tacc = tc == DType::F64 ? DType::F64 : DType::F32;
   const int pb = RISP_NPHASE * (bf ? RISP_BF16 : (tc == DType::F32 ? RISP_FP32 : RISP_FP64));  // profile slots
-  ensure_workspace(f, m, tc, s);
   const int64_t ov = (int64_t)f->nocc * f->nvir;
   const int nJ = f->naux_j;
   const int64_t ldt = f->ld_ia;  // padded row stride of T_ia
@@ -778,12 +795,12 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   if (f->j_mode == RISP_J_AO_DIRECT) {
     coulomb_ao(f, m, X, tv, sig, pb, s);
   } else if (bf) {
-    need(f->ws_xbf, (size_t)m * ldt * 2, "X (BF16)");
-    need(f->ws_ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 2, "Yt (BF16)");
+    need(w.xbf, (size_t)m * ldt * 2, "X (BF16)");
+    need(w.ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 2, "Yt (BF16)");
     // BF16 copy of X with the row stride of T_ia (zero padding), then the two skinny passes
     {
       PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0, 6.0 * m * ov);
-      store_rows_padded(X, DType::F32, ov, m, ov, f->ws_xbf.get(), DType::BF16, ldt, nullptr, 1, 1, s);
+      store_rows_padded(X, DType::F32, ov, m, ov, w.xbf.get(), DType::BF16, ldt, nullptr, 1, 1, s);
     }
     const int nJp = (int)pad_to(nJ, 32);
     for (int g0 = 0; g0 < m; g0 += kCoulombMaxM) {
@@ -793,26 +810,26 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
         PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * mg,
                       2.0 * ((double)nJ * ov + (double)mg * ov) + 4.0 * nJ * mg);
         coulomb_y_bf16(static_cast<const uint16_t*>(Tia), nJ, ldt,
-                       static_cast<const uint16_t*>(f->ws_xbf.get()) + (size_t)g0 * ldt, mg,
-                       f->scale_ia2.as<float>(), f->ws_split.as<float>(), f->ws_split.bytes(),
-                       static_cast<uint16_t*>(f->ws_ybf.get()), nJp, s);
+                       static_cast<const uint16_t*>(w.xbf.get()) + (size_t)g0 * ldt, mg,
+                       f->scale_ia2.as<float>(), w.split.as<float>(), w.split.bytes(),
+                       static_cast<uint16_t*>(w.ybf.get()), nJp, s);
       }
       {
         // pass 2: sigma[m][ia] = 2 sum_P Yt[m][P] T_ia[P][ia]
         PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * mg,
                       2.0 * (double)nJ * ov + 4.0 * (double)mg * ov);
         coulomb_j_bf16(static_cast<const uint16_t*>(Tia), nJ, ldt, ov,
-                       static_cast<const uint16_t*>(f->ws_ybf.get()), nJp, mg, 2.0f,
+                       static_cast<const uint16_t*>(w.ybf.get()), nJp, mg, 2.0f,
                        static_cast<float*>(sig) + (size_t)g0 * ov, s);
       }
     }
   } else if (tc == DType::F32) {
     // FP32 copy of X with the row stride of T_ia (zero padding), then the two skinny FP32 passes
-    need(f->ws_xbf, (size_t)m * ldt * 4, "X (padded)");
-    need(f->ws_ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 4, "Yt");
+    need(w.xbf, (size_t)m * ldt * 4, "X (padded)");
+    need(w.ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 4, "Yt");
     {
       PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0, 8.0 * m * ov);
-      store_rows_padded(X, DType::F32, ov, m, ov, f->ws_xbf.get(), DType::F32, ldt, nullptr, 1, 1, s);
+      store_rows_padded(X, DType::F32, ov, m, ov, w.xbf.get(), DType::F32, ldt, nullptr, 1, 1, s);
     }
     const int nJp = (int)pad_to(nJ, 32);
     for (int g0 = 0; g0 < m; g0 += kCoulombMaxM) {
@@ -820,18 +837,18 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       {
         PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * mg,
                       4.0 * ((double)nJ * ov + (double)mg * ov) + 4.0 * nJ * mg);
-        coulomb_y_f32(static_cast<const float*>(Tia), nJ, ldt, f->ws_xbf.as<float>() + (size_t)g0 * ldt, mg,
-                      f->ws_split.as<float>(), f->ws_split.bytes(), f->ws_ybf.as<float>(), nJp, s);
+        coulomb_y_f32(static_cast<const float*>(Tia), nJ, ldt, w.xbf.as<float>() + (size_t)g0 * ldt, mg,
+                      w.split.as<float>(), w.split.bytes(), w.ybf.as<float>(), nJp, s);
       }
       {
         PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_J, 2.0 * nJ * (double)ov * mg,
                       4.0 * (double)nJ * ov + 4.0 * (double)mg * ov);
-        coulomb_j_f32(static_cast<const float*>(Tia), nJ, ldt, ov, f->ws_ybf.as<float>(), nJp, mg, 2.0f,
+        coulomb_j_f32(static_cast<const float*>(Tia), nJ, ldt, ov, w.ybf.as<float>(), nJp, mg, 2.0f,
                       static_cast<float*>(sig) + (size_t)g0 * ov, s);
       }
     }
   } else {
-    need(f->ws_y, (size_t)nJ * m * dtype_size(tacc), "Y");
+    need(w.y, (size_t)nJ * m * dtype_size(tacc), "Y");
     // Coulomb pass 1: Y[P][m] = sum_ia T_ia[P][ia] X[m][ia]   (split over ia)
     {
       PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y, 2.0 * nJ * (double)ov * m,
@@ -847,11 +864,12 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g.lda = ldt;
       g.B = X;
       g.ldb = ov;
-      g.C = f->ws_y.get();
+      g.C = w.y.get();
       g.ldc = m;
       g.ksplit = std::min(kMaxSplit, gemm_auto_split(g));
-      need(f->ws_split, gemm_workspace_bytes(g), "split-K");
-      gemm(g, f->ws_split.get(), s);
+      while (g.ksplit > 1 && gemm_workspace_bytes(g) > w.split.bytes()) --g.ksplit;
+      need(w.split, gemm_workspace_bytes(g), "split-K");
+      gemm(g, w.split.get(), s);
     }
     // Coulomb pass 2: sigma[m][ia] = 2 sum_P Y[P][m] T_ia[P][ia]
     {
@@ -863,7 +881,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g.K = nJ;
       g.tin = tc;
       g.tout = tv;
-      g.A = f->ws_y.get();  // A[mm][P] = Y[P][mm]
+      g.A = w.y.get();  // A[mm][P] = Y[P][mm]
       g.lda = m;
       g.a_kc = false;
       g.B = Tia;  // B[ia][P] = T[P][ia]
@@ -884,16 +902,16 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
     // P-chunk from the budget rule alone (not from the workspace capacity, which depends on earlier
     // calls), so the summation order depends only on the inputs
     const int64_t per_p = (int64_t)m * nvk * nokp;
-    const int pc = (int)mt_chunk(nK, per_p, (int64_t)csz);
-    need(f->ws_mt, (size_t)per_p * pc * csz, "exchange intermediate");
-    need(f->ws_xw, (size_t)m * nokp * nvkp * csz, "Xw");
-    need(f->ws_k, (size_t)m * nok * nvk * dtype_size(tacc), "K");
+    const int pc = (int)mt_chunk(nK, per_p, (int64_t)csz, w.mt_budget);
+    need(w.mt, (size_t)per_p * pc * csz, "exchange intermediate");
+    need(w.xw, (size_t)m * nokp * nvkp * csz, "Xw");
+    need(w.k, (size_t)m * nok * nvk * dtype_size(tacc), "K");
     {
       // window block of X, rows and columns padded with zeros ([m][nokp][nvkp])
       PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0,
                     (double)m * nok * nvk * dtype_size(tv) + (double)m * nokp * nvkp * csz);
       gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
-                    f->ws_xw.get(), tc, nokp, nvkp, s);
+                    w.xw.get(), tc, nokp, nvkp, s);
     }
     for (int P0 = 0; P0 < nK; P0 += pc) {
       const int np = std::min(pc, nK - P0);
@@ -911,9 +929,9 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g1.tout = tc;
       g1.A = static_cast<const char*>(Tab) + (size_t)P0 * nvk * nvkp * csz;
       g1.lda = nvkp;
-      g1.B = f->ws_xw.get();
+      g1.B = w.xw.get();
       g1.ldb = nvkp;
-      g1.C = f->ws_mt.get();
+      g1.C = w.mt.get();
       g1.ldc = (int64_t)np * nokp;
       g1.nb2 = np;
       g1.sa2 = (int64_t)nvk * nvkp;
@@ -936,22 +954,101 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
       g2.tout = tacc;
       g2.A = static_cast<const char*>(Tij) + (size_t)P0 * nokp * csz;
       g2.lda = (int64_t)nK * nokp;
-      g2.B = f->ws_mt.get();
+      g2.B = w.mt.get();
       g2.ldb = (int64_t)np * nokp;
-      g2.C = f->ws_k.get();
+      g2.C = w.k.get();
       g2.ldc = nvk;
       g2.n_inner = nvk;
       g2.sc_outer = (int64_t)nok * nvk;
       g2.beta = P0 > 0 ? 1.0 : 0.0;
       g2.ksplit = std::max(1, std::min(kMaxSplitK, gemm_auto_split(g2)));
-      if (g2.ksplit > 1) need(f->ws_split, gemm_workspace_bytes(g2), "split-K (exchange)");
-      gemm(g2, g2.ksplit > 1 ? f->ws_split.get() : nullptr, s);
+      while (g2.ksplit > 1 && gemm_workspace_bytes(g2) > w.split.bytes()) --g2.ksplit;
+      if (g2.ksplit > 1) need(w.split, gemm_workspace_bytes(g2), "split-K (exchange)");
+      gemm(g2, g2.ksplit > 1 ? w.split.get() : nullptr, s);
     }
   }
   PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, (double)m * ov * 3.0,
                 (double)m * ov * dtype_size(tv) * 3.0 + (double)m * nok * nvk * dtype_size(tacc));
   combine_sigma(sig, X, tv, f->de64.as<double>(), f->de32.as<float>(), m, f->nocc, f->nvir,
-                exch ? f->ws_k.get() : nullptr, tacc, f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk, s);
+                exch ? w.k.get() : nullptr, tacc, f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk, s);
+}
+
+
+void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s) {
+  if (m <= 0) return;
+  const bool bf = f->precision == RISP_BF16 && !use_f32;
+  const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
+  ensure_workspace(f, m, tc, s);
+  SigmaWs w;
+  w.y = {f->ws_y.get(), f->ws_y.bytes()};
+  w.ybf = {f->ws_ybf.get(), f->ws_ybf.bytes()};
+  w.xbf = {f->ws_xbf.get(), f->ws_xbf.bytes()};
+  w.xw = {f->ws_xw.get(), f->ws_xw.bytes()};
+  w.mt = {f->ws_mt.get(), f->ws_mt.bytes()};
+  w.k = {f->ws_k.get(), f->ws_k.bytes()};
+  w.split = {f->ws_split.get(), f->ws_split.bytes()};
+  sigma_run(f, m, X, sig, use_f32, s, w);
+}
+
+// Lays the sigma workspaces of m vectors (stored-precision products) out in [base, base + cap),
+// each piece 256-byte aligned: Y or (Yt, padded X); the window block and the exchange accumulator;
+// then, of what is left, three quarters for the exchange intermediate (whole auxiliary functions,
+// at least one) and the rest for split-K partial sums (at least what the Coulomb pass needs).
+// Returns 0 when it fits, else the bytes of the smallest layout.
+static size_t carve_scratch(const risp_factors* f, int m, SigmaWs& w, char* base, size_t cap) {
+  const DType tc = f->precision == RISP_FP64 ? DType::F64 : (f->precision == RISP_BF16 ? DType::BF16 : DType::F32);
+  const size_t csz = dtype_size(tc), acc = tc == DType::F64 ? 8 : 4;
+  const int nJ = f->naux_j;
+  auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+  size_t off = 0;
+  auto take = [&](WsView& v, size_t bytes) {
+    v = {base && bytes ? base + off : nullptr, bytes};
+    off += up(bytes);
+  };
+  size_t split_min = 0;
+  if (tc == DType::F64) {
+    take(w.y, (size_t)nJ * m * acc);
+  } else {
+    const size_t xe = tc == DType::BF16 ? 2 : 4;
+    take(w.ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * xe + 16);
+    take(w.xbf, (size_t)m * f->ld_ia * xe + 16);
+    split_min = coulomb_y_workspace(nJ, std::min(m, kCoulombMaxM), f->ld_ia);
+  }
+  const bool exch = f->naux_k > 0 && f->nok > 0 && f->nvk > 0;
+  const size_t per_p = exch ? (size_t)m * f->nvk * f->nokp * csz : 0;  // intermediate bytes per function
+  if (exch) {
+    take(w.xw, (size_t)m * f->nokp * f->nvkp * csz);
+    take(w.k, (size_t)m * f->nok * f->nvk * acc);
+  }
+  const size_t smallest = off + up(per_p) + up(split_min);
+  if (smallest > cap) return smallest;
+  size_t rest = cap - off;
+  if (exch) {
+    const size_t share = std::max(per_p, (rest - up(split_min)) / 4 * 3);
+    const int64_t pc = std::min<int64_t>(f->naux_k, (int64_t)(share / per_p));
+    take(w.mt, (size_t)pc * per_p);
+    w.mt_budget = (int64_t)(pc * per_p);
+    rest = cap - off;
+  }
+  w.split = {base ? base + off : nullptr, rest};
+  return 0;
+}
+
+size_t sigma_scratch_need(const risp_factors* f, int m, size_t cap) {
+  SigmaWs w;
+  return carve_scratch(f, m, w, nullptr, cap);
+}
+
+void sigma_scratch(risp_factors* f, int m, const void* X, void* sig, void* base, size_t cap, hipStream_t s) {
+  if (m <= 0) return;
+  RISP_CHECK(f->j_mode == RISP_J_MO, RISP_E_ARG,
+             "the scratch-buffer sigma supports the stored-factor Coulomb route only");
+  SigmaWs w;
+  const size_t need_bytes = carve_scratch(f, m, w, static_cast<char*>(base), cap);
+  RISP_CHECK(need_bytes == 0, RISP_E_SHAPE,
+             "sigma of " + std::to_string(m) + " vectors needs at least " + std::to_string(need_bytes) +
+                 " bytes of scratch; the fixed scratch holds " + std::to_string(cap));
+  sigma_run(f, m, X, sig, false, s, w);
 }
 
 }  // namespace risp

@@ -24,6 +24,7 @@ struct risp_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   risp::DevBuf boys;                // Boys-function Taylor table
+  void* scratch = nullptr;          // this device's copy of the library's fixed scratch array
   std::set<risp_factors*> factors;  // live factor objects (detached when the context goes away)
   bool profiling = false;
   risp::PhaseLog phase[RISP_NPHASE_SLOTS];
@@ -96,6 +97,12 @@ constexpr int kAoMaxNao = 16384;
 // precision of the sigma arithmetic: FP64 factors -> FP64, FP32 -> FP32, BF16 -> BF16 with FP32
 // accumulation; `use_f32` selects the FP32 copies of BF16 factors.
 void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s);
+
+// sigma in the stored precision with every workspace taken from [scratch, scratch + cap): no
+// allocation. Throws RISP_E_SHAPE when m vectors do not fit (sigma_scratch_need gives the bytes of
+// the smallest layout, 0 when it fits). The stored-factor Coulomb route only.
+void sigma_scratch(risp_factors* f, int m, const void* X, void* sig, void* scratch, size_t cap, hipStream_t s);
+size_t sigma_scratch_need(const risp_factors* f, int m, size_t cap);
 
 // size the sigma workspaces for m vectors ahead of a graph capture (their allocation synchronises)
 void sigma_prepare(risp_factors* f, int m, bool use_f32);

@@ -1,6 +1,8 @@
 // C ABI of librisp (declared in include/risp.h): argument checks, status codes, context and
 // factor objects, and the stage entry points used for validation.
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <cstring>
 #include <string>
 
@@ -44,6 +46,25 @@ void use_ctx(const risp_ctx* ctx) {
   RISP_HIP(hipSetDevice(ctx->device));
 }
 
+// Fixed scratch array of the allocation-free sigma entry point. Each device holds its own copy
+// (allocated when the code object is loaded, kept until the process ends); host code reaches it only
+// through the per-device address from hipGetSymbolAddress, never through the array's name.
+__device__ __align__(256) unsigned char scratch[RISP_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;  // device -> address of its copy
+
+// address of this device's scratch copy (the device must be current)
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  RISP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  RISP_CHECK(p != nullptr, RISP_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_addr[device] = p;
+  return p;
+}
+
 double seconds_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -82,6 +103,7 @@ risp_status risp_ctx_create(int32_t device, void* hip_stream, risp_ctx** out) {
       boys_table_host(tab);
       c->boys = upload(tab.data(), tab.size(), c->stream);
       RISP_HIP(hipStreamSynchronize(c->stream));
+      c->scratch = scratch_address(device);
     } catch (...) {
       if (c->own_stream) (void)hipStreamDestroy(c->stream);
       delete c;
@@ -332,6 +354,33 @@ risp_status risp_sigma(risp_ctx* ctx, const risp_factors* fc, int32_t m, const v
     RISP_CHECK(dtype == want, RISP_E_ARG,
                want == RISP_FP64 ? "FP64 factors take FP64 vectors" : "FP32/BF16 factors take FP32 vectors");
     sigma(const_cast<risp_factors*>(fc), m, X_dev, sigma_dev, false, fc->stream);
+    return RISP_OK;
+  });
+}
+
+risp_status risp_sigma_noalloc(risp_ctx* ctx, const risp_factors* fc, int32_t m, const void* X_dev,
+                               void* sigma_dev, int32_t dtype) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(fc != nullptr, RISP_E_ARG, "factors are NULL");
+    RISP_CHECK(fc->ctx == ctx, RISP_E_STATE, "factors belong to another context");
+    RISP_CHECK(m >= 0, RISP_E_ARG, "m must be non-negative");
+    RISP_CHECK(m == 0 || (X_dev && sigma_dev), RISP_E_ARG, "NULL device buffer");
+    const int want = fc->precision == RISP_FP64 ? RISP_FP64 : RISP_FP32;
+    RISP_CHECK(dtype == want, RISP_E_ARG,
+               want == RISP_FP64 ? "FP64 factors take FP64 vectors" : "FP32/BF16 factors take FP32 vectors");
+    RISP_CHECK(ctx->scratch != nullptr, RISP_E_STATE, "context has no scratch address");
+    // no phase events either: event creation is left out of this path
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    try {
+      sigma_scratch(const_cast<risp_factors*>(fc), m, X_dev, sigma_dev, ctx->scratch, RISP_SCRATCH_BYTES,
+                    fc->stream);
+    } catch (...) {
+      ctx->profiling = prof;
+      throw;
+    }
+    ctx->profiling = prof;
     return RISP_OK;
   });
 }
