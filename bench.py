@@ -1,16 +1,16 @@
 """Benchmark of the TDA-risp hot path on one MI355X.
 
-A step is one pass of the whole path over one synthetic molecule: the factor build
-(risp_build_factors) followed by the Davidson solve to 15 states (risp_davidson), i.e. the
-time-to-15-states. The default workload is the 300-atom chain-and-ring molecule (180 C + 120 H,
-nao 2220, nocc 450, nvir 1770, 720 Coulomb and 180 exchange auxiliary functions, 40 eV window,
-blocks of 30 trial vectors). The BF16 path (BF16 MFMA products with FP32 accumulation, per-slice
-power-of-two scales, FP32 correction pass) is the timed value; the plain FP32 path is timed beside
-it. `value` is the sigma-build throughput (algorithmic flops of all sigma blocks / their time) of
-the BF16 steps; `ms_per_step` is the BF16 time-to-15-states.
+Default workload: the 1000-atom chain-and-ring molecule (600 C + 400 H; nao 7400, nocc 1500,
+nvir 5900, 2400 Coulomb and 600 exchange auxiliary functions, 40 eV window). A step is one sigma
+block of 30 trial vectors (risp_sigma: diagonal, Coulomb and windowed exchange, BF16 MFMA products
+with FP32 accumulation and per-slice power-of-two scales) on the BF16 factors, which are built once
+before the timed steps; `value` is its sigma-build throughput (algorithmic flops of the block / its
+time) and `ms_per_step` its time. Beside the steps, each path runs once end to end from the inputs
+to 15 converged states (factor build + Davidson, with the FP32 correction pass on the BF16 path):
+`time_to_15_states_s` for BF16 and plain FP32, with the phase breakdown, and one FP32 sigma block.
 
-Prints one JSON line. Inputs are generated on the host before the timed region; the factor build
-takes the MO coefficients from host memory (the PCIe copy of C is inside the timed step).
+Prints one JSON line. Inputs are generated on the host before any timed region; the factor build
+takes the MO coefficients from host memory (their PCIe copy is inside the time-to-15-states).
 """
 from __future__ import annotations
 
@@ -30,17 +30,20 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="chainring300")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chainring1000")
+    ap.add_argument("--m", type=int, default=30, help="trial vectors per timed sigma block")
+    ap.add_argument("--no-t2s", action="store_true", help="skip the end-to-end time-to-15-states runs")
     ap.add_argument("--nstates", type=int, default=15)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison steps")
     ap.add_argument("--no-bf16", action="store_true", help="time only the plain FP32 path (long workloads)")
     ap.add_argument("--verbose", action="store_true", help="one stderr line per Davidson iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ao", action="store_true", help="skip the AO-density Coulomb route sigma block")
-    ap.add_argument("--cpu-sample-aux", type=int, default=144, help="exchange auxiliary slices in the CPU sample")
+    ap.add_argument("--ao", action="store_true", help="also time one AO-density Coulomb route sigma block")
+    ap.add_argument("--cpu-sample-aux", type=int, default=0,
+                    help="exchange auxiliary slices in the CPU sample (0: sized for about 15 s on 16 cores)")
     ap.add_argument("--no-serving", action="store_true", help="skip the 64-job serving stream (the default)")
     ap.add_argument("--serving", action="store_true",
                     help="also run the 64-job serving stream (off by default: its run ended in a host "
@@ -52,40 +55,45 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(mol, nsample_k, m=30, repeat=1):
+def cpu_baseline(mol, nsample_k=0, m=30, gpu_flops=None, target_flops=1.5e13):
     """The FP64 oracle's sigma product on a bounded sample of the same workload.
 
-    The sample keeps the full orbital dimensions (nocc, nvir, window) and m = 30 trial vectors, and
-    takes the first `nsample_k` exchange and 4 * nsample_k Coulomb auxiliary slices (random factor
-    values: the oracle's cost does not depend on them). Reported as sigma-build GFLOP/s in the same
-    flop convention as the GPU value.
+    The sample keeps the full orbital dimensions (nocc, nvir, window) and m trial vectors and takes
+    the first nsample_k exchange and 4 * nsample_k Coulomb auxiliary slices (random factor values:
+    the oracle's cost does not depend on them); nsample_k = 0 sizes it for target_flops (about 15 s
+    on 16 host cores). Reported as sigma-build TFLOP/s in the same flop convention as the GPU value,
+    with the oracle's full sigma block extrapolated from it.
     """
     import numpy as np
     from oracle import risp as R
     rng = np.random.default_rng(7)
     nocc, nvir = mol.nocc, mol.nvir
     occK, virK = R.window_sets(mol.mo_energy, nocc, 40.0)
+    ov, nok, nvk = nocc * nvir, len(occK), len(virK)
+    per_k = 4.0 * ov * 4 * m + 2.0 * nok * nvk * m * (nok + nvk)  # one exchange + four Coulomb slices
+    if nsample_k <= 0:
+        nsample_k = int(max(1, min(600, target_flops // per_k)))
     nj = 4 * nsample_k
     F = R.Factors(nocc=nocc, nvir=nvir, de=(mol.mo_energy[None, nocc:] - mol.mo_energy[:nocc, None]),
                   B_ia=rng.standard_normal((nj, nocc, nvir)) * 1e-2,
-                  Bx_ij=rng.standard_normal((nsample_k, len(occK), len(occK))) * 1e-2,
-                  Bx_ab=rng.standard_normal((nsample_k, len(virK), len(virK))) * 1e-2, occK=occK, virK=virK)
+                  Bx_ij=rng.standard_normal((nsample_k, nok, nok)) * 1e-2,
+                  Bx_ab=rng.standard_normal((nsample_k, nvk, nvk)) * 1e-2, occK=occK, virK=virK)
     X = rng.standard_normal((m, nocc, nvir))
     t0 = time.perf_counter()
-    for _ in range(repeat):
-        R.sigma(F, X)
-    dt = (time.perf_counter() - t0) / repeat
-    ov = nocc * nvir
-    nok, nvk = len(occK), len(virK)
+    R.sigma(F, X)
+    dt = time.perf_counter() - t0
     flops = 4.0 * ov * nj * m + 2.0 * nsample_k * nok * nvk * m * (nok + nvk) + ov * m
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"one FP64 sigma block (m={m}) with {nsample_k} of the exchange and {nj} of the Coulomb "
-                      f"auxiliary slices at full nocc/nvir/window, {dt:.1f} s",
-            "seconds": dt, "flops": flops}
+    out = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"one FP64 sigma block (m={m}) with {nsample_k} of the exchange and {nj} of the Coulomb "
+                     f"auxiliary slices at full nocc/nvir/window, {dt:.1f} s",
+           "seconds": dt, "flops": flops}
+    if gpu_flops:
+        out["full_sigma_block_s_extrapolated"] = gpu_flops / (flops / dt)
+    return out
 
 
 def _gen_k(item):
@@ -167,7 +175,16 @@ def serving_bench(jobs, tol=1e-5, max_active=8):
             "max_active": max_active, "mean_gap_s": 0.5}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "exchange_m_chainring300_traffic.json")
+def sigma_block_flops(d, m):
+    """Algorithmic flops of one sigma block of m vectors (stored-factor Coulomb route): diagonal
+    ov*m, Coulomb 4*ov*naux_J*m (two passes over T_ia), exchange 2*nK*noK*nvK*m*(noK + nvK)."""
+    ov = d.nocc * d.nvir
+    return (ov * m + 4.0 * ov * d.naux_j * m +
+            2.0 * d.naux_k * d.nocc_k * d.nvir_k * m * (d.nocc_k + d.nvir_k))
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"exchange_m_{workload}_traffic.json")
 
 
 def _source_digest():
@@ -176,13 +193,14 @@ def _source_digest():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the exchange kernel from the committed counter runs, or None when the
-    kernel source changed since they were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def recorded_traffic(workload, m):
+    """HBM bytes per launch of the exchange kernel from the committed counter runs for this workload
+    and block size, or None when there are none or the kernel source changed since they were taken."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
         return None
-    rec = json.load(open(TRAFFIC_FILE))
-    if rec.get("kernel_source_sha256_16") != _source_digest():
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256_16") != _source_digest() or rec.get("m", m) != m:
         return None
     return rec.get("bytes_per_launch")
 
@@ -220,6 +238,24 @@ def ao_route_block(ctx, P, sysc, torch, m=30):
     return out
 
 
+def sigma_rows_check(ctx, F, P, torch, workload, m):
+    """Max error of this GPU's sigma at the oracle's sampled rows (tests/golden/<workload>_sigma_rows.json,
+    written by the FP64 oracle alone), relative to the largest sampled element; None without the file."""
+    import numpy as np
+
+    import synth
+    gold = os.path.join(ROOT, "tests", "golden", f"{workload}_sigma_rows.json")
+    if not os.path.exists(gold):
+        return None
+    g = json.load(open(gold))
+    d = F.desc
+    X = torch.tensor(synth.random_trial_vectors(len(g["sigma"]), d.nocc, d.nvir, g["seed"]), dtype=torch.float32,
+                     device=ctx.device)
+    S = ctx.sigma(F, X).reshape(X.shape[0], -1)[:, torch.tensor(g["rows"], device=ctx.device)].cpu().numpy()
+    want = np.array(g["sigma"])
+    return float(np.abs(S - want).max() / np.abs(want).max())
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -235,14 +271,20 @@ def main():
     import paper_2603_29257_amd as P
     import synth
 
+    def log(msg):
+        print(f"# {msg}", file=sys.stderr, flush=True)
+
     t_gen = time.perf_counter()
     mol = synth.config_system(args.workload)
     jobs = serving_jobs(args.serving_jobs) if (args.serving and not args.no_serving) else None
     t_gen = time.perf_counter() - t_gen
+    log(f"{args.workload}: nao {mol.nao}, nocc {mol.nocc}, nvir {mol.nvir}; generated in {t_gen:.1f} s")
     ctx = P.Context(0)
     sysc = P.System(mol)
+    m = args.m
 
-    def step(prec, profile=False):
+    def t2s(prec):
+        """Inputs on the host -> factors -> Davidson to nstates converged states; the factors stay."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = ctx.build_factors(sysc, P.Params(precision=P.PRECISIONS[prec]))
@@ -250,43 +292,66 @@ def main():
                                   verbose=args.verbose)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        desc = F.desc
-        F.free()
-        return dt, e, info, desc
+        log(f"{prec} time-to-{args.nstates}-states {dt:.2f} s (build {info.t_build:.2f} s, "
+            f"{info.iters}+{info.correction_iters} iterations, converged={info.converged})")
+        return F, dict(t2s=dt, energies=[float(x) for x in e], iters=info.iters,
+                       correction_iters=info.correction_iters, converged=bool(info.converged),
+                       breakdown={"build": info.t_build, "sigma": info.t_sigma, "subspace": info.t_subspace,
+                                  "correction": info.t_correct},
+                       sigma_tflops=info.sigma_flops / info.t_sigma / 1e12 if info.t_sigma > 0 else None,
+                       sigma_tflops_correction=(info.sigma_flops_correct / info.t_sigma_correct / 1e12
+                                                if info.t_sigma_correct > 0 else None))
 
+    def sigma_blocks(F, n, warm):
+        """n timed sigma blocks of m vectors (after `warm` untimed ones); returns seconds per block."""
+        d = F.desc
+        X = torch.tensor(synth.random_trial_vectors(m, d.nocc, d.nvir, 2603), dtype=torch.float32,
+                         device=ctx.device)
+        out = torch.empty_like(X)
+        for _ in range(warm):
+            ctx.sigma(F, X, out=out)
+        torch.cuda.synchronize()
+        times = []
+        for k in range(n):
+            t0 = time.perf_counter()
+            ctx.sigma(F, X, out=out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return times
+
+    res, t2s_res = {}, {}
     precs = ([] if args.no_bf16 else ["bf16"]) + ([] if args.no_fp32 else ["fp32"])
     if not precs:
         sys.exit("nothing to time: --no-bf16 and --no-fp32 together")
+    mp_ = precs[0]  # the path the value and the roofline describe
     for prec in precs:
-        for _ in range(args.warmup):
-            step(prec)
-            print(f"# warmup {prec} done", file=sys.stderr, flush=True)
-    res = {}
-    for prec in precs:
-        ctx.profile(True, True)
-        times, flops, tsig, iters, conv = [], 0.0, 0.0, [], []
-        fl_c, ts_c = 0.0, 0.0
-        for k in range(args.steps):
-            dt, e, info, desc = step(prec)
-            times.append(dt)
-            flops += info.sigma_flops
-            tsig += info.t_sigma
-            fl_c += info.sigma_flops_correct
-            ts_c += info.t_sigma_correct
-            iters.append(info.iters + info.correction_iters)
-            conv.append(info.converged)
-            print(f"# {prec} step {k}: {dt:.3f} s, {info.iters}+{info.correction_iters} iterations, "
-                  f"converged={info.converged}", file=sys.stderr, flush=True)
-        prof = ctx.profile(False, True)
-        res[prec] = dict(t2s=float(np.mean(times)), times=times, sigma_tflops=flops / tsig / 1e12,
-                         sigma_tflops_correction=(fl_c / ts_c / 1e12) if ts_c > 0 else None,
-                         energies=[float(x) for x in e], iters=iters, converged=all(conv), prof=prof,
-                         t_build=info.t_build, t_sigma=info.t_sigma, t_subspace=info.t_subspace,
-                         t_correct=info.t_correct, desc=desc)
+        if args.no_t2s:
+            F = ctx.build_factors(sysc, P.Params(precision=P.PRECISIONS[prec]))
+        else:
+            F, t2s_res[prec] = t2s(prec)
+        d = F.desc
+        flops = sigma_block_flops(F.desc, m)
+        if prec == mp_:
+            for k in range(args.warmup):
+                sigma_blocks(F, 1, 0)
+                log(f"warmup {k}")
+            ctx.profile(True, True)
+            times = []
+            for k in range(args.steps):
+                times += sigma_blocks(F, 1, 0)
+                log(f"{prec} step {k}: {times[-1] * 1e3:.1f} ms, {flops / times[-1] / 1e12:.0f} TFLOP/s")
+            prof = ctx.profile(False, True)
+        else:
+            times = sigma_blocks(F, 1, 1)
+            prof = None
+            log(f"{prec} sigma block: {times[-1] * 1e3:.1f} ms, {flops / times[-1] / 1e12:.0f} TFLOP/s")
+        res[prec] = dict(times=times, flops=flops, prof=prof, desc=d,
+                         sigma_rows_err=sigma_rows_check(ctx, F, P, torch, args.workload, m))
+        F.free()
 
-    mp_ = "bf16" if "bf16" in res else "fp32"  # the path the value and the roofline describe
     b = res[mp_]
-    # dominant kernel of the sigma blocks: the exchange product M = T_ab X (one launch per chunk)
+    t_step = float(np.mean(b["times"]))
+    # dominant kernel of the step: the exchange product M = T_ab X (one launch per auxiliary chunk)
     ph = b["prof"][mp_]["exchange_m"]
     per_launch_ms = ph["ms"] / max(ph["launches"], 1)
     per_launch_flops = ph["flops"] / max(ph["launches"], 1)
@@ -295,51 +360,53 @@ def main():
                 "kernel": ("exchange M^P = T_ab^P X (BF16 MFMA, FP32 accumulate)" if mp_ == "bf16"
                            else "exchange M^P = T_ab^P X (FP32 MFMA)"),
                 "achieved": achieved, "peak": PEAK[mp_], "unit": "TFLOP/s", "frac": achieved / PEAK[mp_],
-                "traffic": recorded_traffic() if (mp_ == "bf16" and args.workload == "chainring300") else None,
+                "traffic": recorded_traffic(args.workload, m) if mp_ == "bf16" else None,
                 "launches": ph["launches"], "avg_launch_ms": per_launch_ms, "flops_per_launch": per_launch_flops}
+
     def phase_table(pr):
         return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                     "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 else 0.0,
                     "gbs": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
                 for k, v in pr.items() if v["launches"] > 0}
-    phases = phase_table(b["prof"][mp_])
-    phases_corr = phase_table(b["prof"]["fp32"]) if mp_ == "bf16" else {}
     d = b["desc"]
+    nsh = len(mol.shells)
     out = {
         "metric": "time-to-15-states & sigma-build TFLOP/s, BF16 vs plain FP32; p50/p99 latency",
-        "value": b["sigma_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": b["t2s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": mp_, "data": "synthetic",
+        "value": b["flops"] / t_step / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": mp_, "data": "synthetic",
         "config": {"workload": args.workload, "atoms": int(mol.natm), "nao": d.nao, "nocc": d.nocc, "nvir": d.nvir,
                    "naux_j": d.naux_j, "naux_k": d.naux_k, "nocc_k": d.nocc_k, "nvir_k": d.nvir_k,
-                   "npair": d.npair, "shell_pairs": len(mol.shells) * (len(mol.shells) + 1) // 2,
-                   "pair_survival_pct": 100.0 * d.npair / (len(mol.shells) * (len(mol.shells) + 1) // 2),
-                   "cond_S": float(mol.cond_S), "nstates": args.nstates, "block": 30, "tol": args.tol,
-                   "window_ev": 40.0, "c_x": 0.22, "beta": 0.78, "omega": 0.2},
-        "time_to_15_states_s": {p: res[p]["t2s"] for p in res},
-        "sigma_tflops": {p: res[p]["sigma_tflops"] for p in res},
-        "sigma_tflops_fp32_correction_stage": res["bf16"]["sigma_tflops_correction"] if "bf16" in res else None,
-        "converged": {p: res[p]["converged"] for p in res},
-        "iterations": {p: res[p]["iters"] for p in res},
-        "breakdown_s": {p: {"build": res[p]["t_build"], "sigma": res[p]["t_sigma"], "subspace": res[p]["t_subspace"],
-                            "correction": res[p]["t_correct"]} for p in res},
-        f"phases_{mp_}": phases,
-        "phases_bf16_job_fp32_correction": phases_corr,
+                   "npair": d.npair, "shell_pairs": nsh * (nsh + 1) // 2,
+                   "pair_survival_pct": 100.0 * d.npair / (nsh * (nsh + 1) // 2),
+                   "cond_S": float(mol.cond_S), "step": f"one sigma block of {m} trial vectors on prebuilt factors",
+                   "m": m, "nstates": args.nstates, "tol": args.tol, "window_ev": 40.0, "c_x": 0.22, "beta": 0.78,
+                   "omega": 0.2},
+        "sigma_block_s": {p: float(np.mean(res[p]["times"])) for p in res},
+        "sigma_tflops": {p: res[p]["flops"] / float(np.mean(res[p]["times"])) / 1e12 for p in res},
+        "sigma_block_flops": b["flops"],
+        "sigma_rows_vs_oracle_rel_err": {p: res[p]["sigma_rows_err"] for p in res},
+        f"phases_{mp_}": phase_table(b["prof"][mp_]),
         "roofline": roofline,
         "latency": None if jobs is None else serving_bench(jobs, tol=args.tol),
         "generator_s": t_gen,
     }
-    if "fp32" in res:
-        out["max_abs_dE_bf16_vs_fp32_ha"] = float(np.max(np.abs(np.array(res["bf16"]["energies"]) -
-                                                               np.array(res["fp32"]["energies"]))))
-    gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.json")
-    if os.path.exists(gold):
-        ref = np.array(json.load(open(gold))["energies_ha"])[:args.nstates]
-        out["max_abs_dE_vs_oracle_ha"] = {p: float(np.max(np.abs(np.array(res[p]["energies"]) - ref))) for p in res}
-    if not args.no_ao:
-        out["ao_route"] = ao_route_block(ctx, P, sysc, torch, m=30)
+    if t2s_res:
+        out["time_to_15_states_s"] = {p: t2s_res[p]["t2s"] for p in t2s_res}
+        out["t2s_detail"] = t2s_res
+        if "bf16" in t2s_res and "fp32" in t2s_res:
+            out["t2s_bf16_over_fp32"] = t2s_res["bf16"]["t2s"] / t2s_res["fp32"]["t2s"]
+            out["max_abs_dE_bf16_vs_fp32_ha"] = float(np.max(np.abs(np.array(t2s_res["bf16"]["energies"]) -
+                                                                   np.array(t2s_res["fp32"]["energies"]))))
+        gold = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.json")
+        if os.path.exists(gold):
+            ref = np.array(json.load(open(gold))["energies_ha"])[:args.nstates]
+            out["max_abs_dE_vs_oracle_ha"] = {p: float(np.max(np.abs(np.array(t2s_res[p]["energies"]) - ref)))
+                                              for p in t2s_res}
+    if args.ao:
+        out["ao_route"] = ao_route_block(ctx, P, sysc, torch, m=m)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mol, args.cpu_sample_aux)
+        out["cpu_baseline"] = cpu_baseline(mol, args.cpu_sample_aux, m=m, gpu_flops=b["flops"])
     ctx.close()
     print(json.dumps(out))
 
