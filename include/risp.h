@@ -170,6 +170,10 @@ typedef struct {
                              storage: e_a - e_i + 2 sum_P B_ia^2 - [window] sum_P Bx_ii Bx_aa (the
                              Coulomb part is left out on the AO route); Davidson guess and
                              preconditioner */
+  const void *t_ij_lo;    /* BF16 factors: dev BF16 remainders of t_ij and t_ab in their layouts
+                             (same scales; T / scale = hi + lo to about 2^-17), used by the
+                             correction pass's split-BF16 exchange; NULL otherwise */
+  const void *t_ab_lo;
 } risp_factors_desc;
 
 /* Per-phase timing of sigma products (HIP events on the context stream around each launch). */
@@ -287,6 +291,29 @@ risp_status risp_sigma(risp_ctx *ctx, const risp_factors *f, int32_t m, const vo
  * threads, two contexts) race, so serialise them. Stream-ordered, no synchronisation. */
 risp_status risp_sigma_noalloc(risp_ctx *ctx, const risp_factors *f, int32_t m, const void *X_dev,
                                void *sigma_dev, int32_t dtype);
+
+/* Transition properties of nstates excited states (eq. oscillator_strength, eq. rotator_strength,
+ * eq. transition and eq. transition_magnetic in the dipole-length form with TDA amplitudes, Y = 0):
+ *   mu_0n = sqrt(2) sum_ia <i| r - O |a> X_nia,   m_0n = sqrt(2) sum_ia <i| (r - O) x nabla |a> X_nia,
+ *   f_0n = 2/3 Omega_n |mu_0n|^2,                 R_0n = 1/2 mu_0n . m_0n,
+ * where sqrt(2) makes the closed-shell singlet of unit-normalised amplitudes X (as risp_davidson
+ * returns them) and (r - O) x nabla is taken as the real antisymmetric operator over the real MOs.
+ * sys: the same system as for the factor build (geometry, AO shells, MO coefficients; the auxiliary
+ * fields are not used); origin: host [3] gauge origin in bohr (NULL: 0, 0, 0); energies: host
+ * [nstates] Hartree; X_dev: device FP32 [nstates][nocc][nvir]. Outputs (host, caller-allocated):
+ * mu [nstates][3] and mdip [nstates][3] (either may be NULL), f [nstates], R [nstates]. AO
+ * integrals by Obara-Saika on the device, FP64 MFMA transforms; allocates device memory and
+ * synchronises the context stream. */
+risp_status risp_properties(risp_ctx *ctx, const risp_system *sys, const double *origin, int32_t nstates,
+                            const double *energies, const void *X_dev, double *mu, double *mdip, double *f,
+                            double *R);
+
+/* Lorentzian-broadened stick spectrum (the paper's UV-vis and ECD figures; half width at half
+ * maximum hwhm, unit-area lines): out[q] = sum_n s_n (hwhm/pi) / ((e0 + q de - E_n)^2 + hwhm^2)
+ * for q < npts. energies and strengths: host [nstates] (f for UV-vis, R for ECD, in any consistent
+ * energy unit); out: host [npts]. Synchronises the context stream. */
+risp_status risp_spectrum(risp_ctx *ctx, int32_t nstates, const double *energies, const double *strengths,
+                          double hwhm, double e0, double de, int32_t npts, double *out);
 
 /* Lowest nstates eigenpairs of A by block Davidson (section on large-system Davidson
  * diagonalisation): guess and preconditioner from the diagonal of A, sigma blocks on MFMA, FP64

@@ -50,30 +50,36 @@ def _one_dim(i, j, A, B, a, b, O):
 
 
 def ao_dipole_and_rxdel(coords, shells, origin=(0.0, 0.0, 0.0)):
-    """AO matrices <mu| r - O |nu> [3][nao][nao] and <mu| (r - O) x nabla |nu> [3][nao][nao]."""
+    """AO matrices <mu| r - O |nu> [3][nao][nao] and <mu| (r - O) x nabla |nu> [3][nao][nao].
+
+    Evaluated for all shell pairs of one angular-momentum class at a time (arrays over the pairs)."""
     coords = np.asarray(coords, dtype=np.float64)
     O = np.asarray(origin, dtype=np.float64)
     off, nao = I.shell_offsets(shells)
+    off = np.array(off)
+    ls = np.array([s[1] for s in shells])
+    cen = np.array([coords[s[0]] for s in shells]).reshape(-1, 3)
+    ex = np.array([s[2] for s in shells], dtype=np.float64)
+    cf = np.array([s[3] for s in shells], dtype=np.float64)
     dip = np.zeros((3, nao, nao))
     rxd = np.zeros((3, nao, nao))
-    for sa, (ka, la, ea, ca) in enumerate(shells):
-        A = coords[ka]
-        for sb, (kb, lb, eb, cb) in enumerate(shells):
-            B = coords[kb]
-            mu = ea * eb / (ea + eb)
-            K = math.exp(-mu * float(np.dot(A - B, A - B)))
+    for la in (0, 1):
+        for lb in (0, 1):
+            SA, SB = np.nonzero(ls == la)[0], np.nonzero(ls == lb)[0]
+            if len(SA) == 0 or len(SB) == 0:
+                continue
+            pa, pb = np.meshgrid(SA, SB, indexing="ij")
+            pa, pb = pa.ravel(), pb.ravel()
+            A, B, a, b = cen[pa], cen[pb], ex[pa], ex[pb]
+            mu = a * b / (a + b)
+            K = np.exp(-mu * np.sum((A - B) ** 2, axis=1))
             for ia, compA in enumerate(I.cart_components(la)):
-                na = float(I.primitive_norm(ea, compA)) * ca
+                na = I.primitive_norm(a, compA) * cf[pa]
                 for ib, compB in enumerate(I.cart_components(lb)):
-                    nb = float(I.primitive_norm(eb, compB)) * cb
-                    S, M, D = [], [], []
-                    for d in range(3):
-                        s_, m_, d_ = _one_dim(compA[d], compB[d], A[d], B[d], ea, eb, O[d])
-                        S.append(float(s_))
-                        M.append(float(m_))
-                        D.append(float(d_))
+                    nb = I.primitive_norm(b, compB) * cf[pb]
+                    S, M, D = zip(*[_one_dim(compA[d], compB[d], A[:, d], B[:, d], a, b, O[d]) for d in range(3)])
                     pre = K * na * nb
-                    r, c = off[sa] + ia, off[sb] + ib
+                    r, c = off[pa] + ia, off[pb] + ib
                     dip[0, r, c] = pre * M[0] * S[1] * S[2]
                     dip[1, r, c] = pre * S[0] * M[1] * S[2]
                     dip[2, r, c] = pre * S[0] * S[1] * M[2]

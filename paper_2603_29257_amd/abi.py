@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 EXPORTS = ("risp_last_error", "risp_ctx_create", "risp_ctx_destroy", "risp_ctx_profile", "risp_select_aux", "risp_window",
            "risp_screen", "risp_int2c", "risp_int3c", "risp_build_factors", "risp_factors_query",
-           "risp_factors_free", "risp_sigma", "risp_sigma_noalloc", "risp_davidson", "risp_serve_config", "risp_job_footprint",
+           "risp_factors_free", "risp_sigma", "risp_sigma_noalloc", "risp_properties", "risp_spectrum", "risp_davidson", "risp_serve_config", "risp_job_footprint",
            "risp_submit", "risp_poll", "risp_serve_stats_get", "risp_device_usage")
 
 
@@ -87,7 +87,8 @@ class FactorsDescC(C.Structure):
                 ("npair", C.c_int32), ("precision", C.c_int32), ("bytes", C.c_int64),
                 ("t_ia", C.c_void_p), ("t_ij", C.c_void_p), ("t_ab", C.c_void_p), ("scale_ia", C.c_void_p),
                 ("scale_k", C.c_void_p), ("occ_k", C.c_void_p), ("vir_k", C.c_void_p),
-                ("ld_ia", C.c_int64), ("ld_ij", C.c_int32), ("ld_ab", C.c_int32), ("diag_a", C.c_void_p)]
+                ("ld_ia", C.c_int64), ("ld_ij", C.c_int32), ("ld_ab", C.c_int32), ("diag_a", C.c_void_p),
+                ("t_ij_lo", C.c_void_p), ("t_ab_lo", C.c_void_p)]
 
 
 class ServeOptsC(C.Structure):
@@ -128,6 +129,8 @@ def load_library(path: str = LIBPATH):
         "risp_factors_free": [vp],
         "risp_sigma": [vp, vp, i32, vp, vp, i32],
         "risp_sigma_noalloc": [vp, vp, i32, vp, vp, i32],
+        "risp_properties": [vp, P(SystemC), P(dbl), i32, P(dbl), vp, P(dbl), P(dbl), P(dbl), P(dbl)],
+        "risp_spectrum": [vp, i32, P(dbl), P(dbl), dbl, dbl, dbl, i32, P(dbl)],
         "risp_davidson": [vp, vp, P(DavOptsC), P(dbl), P(C.c_float), P(DavInfoC)],
         "risp_serve_config": [vp, P(ServeOptsC)],
         "risp_job_footprint": [P(SystemC), P(ParamsC), P(DavOptsC), P(C.c_int64)],
@@ -270,6 +273,8 @@ class Factors:
         dt = {FP64: torch.float64, FP32: torch.float32, BF16: torch.bfloat16}[d.precision]
         shapes = {"t_ia": ((d.naux_j, d.ld_ia), dt), "t_ij": ((d.nocc_k, d.naux_k, d.ld_ij), dt),
                   "t_ab": ((d.naux_k, d.nvir_k, d.ld_ab), dt), "scale_ia": ((d.naux_j,), torch.float32),
+                  "t_ij_lo": ((d.nocc_k, d.naux_k, d.ld_ij), torch.bfloat16),
+                  "t_ab_lo": ((d.naux_k, d.nvir_k, d.ld_ab), torch.bfloat16),
                   "scale_k": ((d.naux_k,), torch.float32), "occ_k": ((d.nocc_k,), torch.int32),
                   "vir_k": ((d.nvir_k,), torch.int32), "diag_a": ((d.nocc, d.nvir), torch.float64)}
         shape, dtype = shapes[which]
@@ -285,9 +290,9 @@ class Factors:
             return out
         if which == "t_ia":
             return out[:, :d.nocc * d.nvir].reshape(d.naux_j, d.nocc, d.nvir)
-        if which == "t_ij":
+        if which in ("t_ij", "t_ij_lo"):
             return out[:, :, :d.nocc_k]
-        if which == "t_ab":
+        if which in ("t_ab", "t_ab_lo"):
             return out[:, :, :d.nvir_k]
         return out
 
@@ -429,6 +434,37 @@ class Context:
         cur.wait_stream(self.stream)
         X.record_stream(self.stream)
         out.record_stream(self.stream)
+        return out
+
+    def properties(self, sys: System, energies, X, origin=(0.0, 0.0, 0.0)):
+        """Transition dipoles mu, magnetic terms m [n][3], oscillator strengths f and rotatory strengths R [n]
+        of states with energies [n] (Hartree) and amplitudes X: a contiguous float32 device tensor
+        [n][nocc][nvir]."""
+        import torch
+        e = np.ascontiguousarray(energies, dtype=np.float64)
+        n = len(e)
+        if X.dtype != torch.float32 or X.device != self.device or not X.is_contiguous():
+            raise ValueError(f"X must be a contiguous float32 tensor on {self.device}")
+        if X.dim() != 3 or X.shape[0] != n:
+            raise ValueError("X must have shape [n, nocc, nvir] with n = len(energies)")
+        o = np.ascontiguousarray(origin, dtype=np.float64)
+        mu, md, f, R = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n), np.zeros(n)
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        _check(_LIB.risp_properties(self.handle, C.byref(sys.c), _ptr(o, C.c_double), n, _ptr(e, C.c_double),
+                                    C.c_void_p(X.data_ptr()), _ptr(mu, C.c_double), _ptr(md, C.c_double),
+                                    _ptr(f, C.c_double), _ptr(R, C.c_double)))
+        return mu, md, f, R
+
+    def spectrum(self, energies, strengths, hwhm, e0, de, npts):
+        """Lorentzian-broadened spectrum on the grid e0 + q de, q < npts (host array)."""
+        e = np.ascontiguousarray(energies, dtype=np.float64)
+        st = np.ascontiguousarray(strengths, dtype=np.float64)
+        if e.shape != st.shape:
+            raise ValueError("energies and strengths differ in length")
+        out = np.zeros(int(npts))
+        _check(_LIB.risp_spectrum(self.handle, len(e), _ptr(e, C.c_double), _ptr(st, C.c_double), float(hwhm),
+                                  float(e0), float(de), int(npts), _ptr(out, C.c_double)))
         return out
 
     # ---- serving ----

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librisp.so")
 SOURCES = ["integrals.hip", "gemm.hip", "gemm_bf16.hip", "coulomb.hip", "linalg.hip", "factors.hip", "subspace.hip", "davidson.hip",
-           "serve.hip", "risp_abi.hip"]
+           "serve.hip", "properties.hip", "risp_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}",

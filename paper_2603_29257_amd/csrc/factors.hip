@@ -14,8 +14,8 @@ static size_t shell_bytes(const risp::DevShells& d) {
 }
 
 int64_t risp_factors::bytes() const {
-  return (int64_t)(t_ia.bytes() + t_ij.bytes() + t_ab.bytes() + t_ia32.bytes() + t_ij32.bytes() +
-                   t_ab32.bytes() + scale_ia.bytes() + scale_ia2.bytes() + scale_k.bytes() + occ_k.bytes() +
+  return (int64_t)(t_ia.bytes() + t_ij.bytes() + t_ab.bytes() + t_ia32.bytes() + t_ij_lo.bytes() +
+                   t_ab_lo.bytes() + scale_ia.bytes() + scale_ia2.bytes() + scale_k.bytes() + occ_k.bytes() +
                    vir_k.bytes() + pos_o.bytes() + pos_v.bytes() + de64.bytes() + de32.bytes() + diag64.bytes() +
                    ws_y.bytes() + ws_ybf.bytes() + ws_xbf.bytes() + ws_xw.bytes() + ws_mt.bytes() +
                    ws_k.bytes() + ws_split.bytes() + shell_bytes(ao_sh) + shell_bytes(auxj_sh) + pairs.a.bytes() +
@@ -108,9 +108,10 @@ static Gemm g64(int M, int N, int K) {
 
 // Stored factor: `rows` rows of `cols` values padded to `ldd` (a multiple of 8, zero padding), in the
 // storage precision; BF16 rows are divided by the power-of-two scale of their auxiliary slice
-// (scale index (row / div) % mod). An FP32 copy with the same layout is kept next to BF16 factors.
+// (scale index (row / div) % mod). Next to BF16 factors the BF16 rounding remainder (same layout and
+// scales) is kept when asked for.
 struct Stored {
-  DevBuf main, f32;
+  DevBuf main, lo;
 };
 // default bytes of one FP64 chunk of transformed integrals: a quarter of the free device memory at
 // the start of the build, between 1 and 64 GiB (fewer chunks = fewer passes over the integrals)
@@ -140,7 +141,7 @@ static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t c
   }
 }
 
-static void store_factor(const double* B, int64_t rows, int64_t cols, int64_t ldd, int precision, bool keep_f32,
+static void store_factor(const double* B, int64_t rows, int64_t cols, int64_t ldd, int precision, bool keep_lo,
                          const float* scale, int64_t div, int64_t mod, Stored& out, hipStream_t s) {
   const int64_t n = std::max<int64_t>(rows * ldd, 1);
   if (precision == RISP_FP64) {
@@ -152,9 +153,9 @@ static void store_factor(const double* B, int64_t rows, int64_t cols, int64_t ld
   } else {
     out.main.alloc(n * 2);
     store_rows_padded(B, DType::F64, cols, rows, cols, out.main.get(), DType::BF16, ldd, scale, div, mod, s);
-    if (keep_f32) {
-      out.f32.alloc(n * 4);
-      store_rows_padded(B, DType::F64, cols, rows, cols, out.f32.get(), DType::F32, ldd, nullptr, 1, 1, s);
+    if (keep_lo) {
+      out.lo.alloc(n * 2);
+      store_rows_padded_lo(B, DType::F64, cols, rows, cols, out.main.get(), out.lo.get(), ldd, scale, div, mod, s);
     }
   }
 }
@@ -436,7 +437,8 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     f->nokp = (int)pad8(nok);
     f->nvkp = (int)pad8(nvk);
     // T_ab goes straight to its stored rows in chunks of window virtuals a (as T_ia above)
-    DevBuf& dab = bf ? f->t_ab32 : f->t_ab;
+    DevBuf ab32;  // BF16 mode: FP32 staging of T_ab until the slice scales are known
+    DevBuf& dab = bf ? ab32 : f->t_ab;
     dab.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * dsz);
     fill_zero(dab.get(), dab.bytes(), s);
     DevBuf mxab((size_t)std::max(nK, 1) * 8), tmp;
@@ -498,8 +500,13 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       sab.alloc((size_t)std::max(nK, 1) * sizeof(float));
       pow2_from_max(mxab.as<double>(), nK, prm->bf16_scale != 0, sab.as<float>(), s);
       f->t_ab.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * 2);
-      store_rows_padded(f->t_ab32.get(), DType::F32, f->nvkp, (int64_t)nK * nvk, f->nvkp, f->t_ab.get(), DType::BF16,
+      store_rows_padded(ab32.get(), DType::F32, f->nvkp, (int64_t)nK * nvk, f->nvkp, f->t_ab.get(), DType::BF16,
                         f->nvkp, sab.as<float>(), nvk, nK, s);
+      f->t_ab_lo.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * 2);
+      store_rows_padded_lo(ab32.get(), DType::F32, f->nvkp, (int64_t)nK * nvk, f->nvkp, f->t_ab.get(),
+                           f->t_ab_lo.get(), f->nvkp, sab.as<float>(), nvk, nK, s);
+      RISP_HIP(hipStreamSynchronize(s));
+      ab32.release();  // the correction pass uses hi + lo
     }
     {
       DevBuf Bp((size_t)nK * nok * nok * 8);  // FP64 [i][P][j]
@@ -509,7 +516,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
                    nK, st, s);
       RISP_HIP(hipStreamSynchronize(s));
       f->t_ij = std::move(st.main);
-      f->t_ij32 = std::move(st.f32);
+      f->t_ij_lo = std::move(st.lo);
     }
     if (bf) {
       f->scale_k.alloc(nK * sizeof(float));
@@ -788,9 +795,11 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
   const int64_t ov = (int64_t)f->nocc * f->nvir;
   const int nJ = f->naux_j;
   const int64_t ldt = f->ld_ia;  // padded row stride of T_ia
-  const void* Tia = (f->precision == RISP_BF16 && use_f32) ? f->t_ia32.get() : f->t_ia.get();
-  const void* Tij = (f->precision == RISP_BF16 && use_f32) ? f->t_ij32.get() : f->t_ij.get();
-  const void* Tab = (f->precision == RISP_BF16 && use_f32) ? f->t_ab32.get() : f->t_ab.get();
+  // correction-pass arithmetic of BF16 factors: FP32 Coulomb, split-BF16 exchange
+  const bool split = f->precision == RISP_BF16 && use_f32;
+  const void* Tia = split ? f->t_ia32.get() : f->t_ia.get();
+  const void* Tij = f->t_ij.get();
+  const void* Tab = f->t_ab.get();
   const size_t esz = dtype_size(tc);
   if (f->j_mode == RISP_J_AO_DIRECT) {
     coulomb_ao(f, m, X, tv, sig, pb, s);
@@ -906,12 +915,19 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
     need(w.mt, (size_t)per_p * pc * csz, "exchange intermediate");
     need(w.xw, (size_t)m * nokp * nvkp * csz, "Xw");
     need(w.k, (size_t)m * nok * nvk * dtype_size(tacc), "K");
+    const size_t nxw = (size_t)m * nokp * nvkp;  // elements of one window block
+    const size_t fsz = split ? 2 : csz;  // bytes per stored factor element (split: the BF16 hi part)
     {
-      // window block of X, rows and columns padded with zeros ([m][nokp][nvkp])
+      // window block of X, rows and columns padded with zeros ([m][nokp][nvkp]); split mode: hi and
+      // lo BF16 blocks one after the other
       PhaseScope po(f->ctx, s, pb + RISP_PHASE_OTHER, 0.0,
                     (double)m * nok * nvk * dtype_size(tv) + (double)m * nokp * nvkp * csz);
-      gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
-                    w.xw.get(), tc, nokp, nvkp, s);
+      if (split)
+        gather_window_split(static_cast<const float*>(X), m, f->nocc, f->nvir, f->occ_k.as<int>(), nok,
+                            f->vir_k.as<int>(), nvk, w.xw.get(), w.xw.as<uint16_t>() + nxw, nokp, nvkp, s);
+      else
+        gather_window(X, tv, m, f->nocc, f->nvir, f->occ_k.as<int>(), nok, f->vir_k.as<int>(), nvk,
+                      w.xw.get(), tc, nokp, nvkp, s);
     }
     for (int P0 = 0; P0 < nK; P0 += pc) {
       const int np = std::min(pc, nK - P0);
@@ -925,9 +941,9 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
       g1.M = nvk;
       g1.N = m * nokp;
       g1.K = nvkp;  // the padding columns of T_ab and Xw are zero
-      g1.tin = tc;
-      g1.tout = tc;
-      g1.A = static_cast<const char*>(Tab) + (size_t)P0 * nvk * nvkp * csz;
+      g1.tin = split ? DType::BF16 : tc;
+      g1.tout = split ? DType::BF16 : tc;
+      g1.A = static_cast<const char*>(Tab) + (size_t)P0 * nvk * nvkp * fsz;
       g1.lda = nvkp;
       g1.B = w.xw.get();
       g1.ldb = nvkp;
@@ -938,7 +954,16 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
       g1.sc2 = nokp;
       g1.n_inner = nokp;
       g1.sc_outer = (int64_t)nvk * np * nokp;
-      g1.batch_scale = bf ? f->scale_k.as<float>() + P0 : nullptr;
+      g1.batch_scale = (bf || split) ? f->scale_k.as<float>() + P0 : nullptr;
+      if (split) {
+        // (hi, hi) + (lo, hi) + (hi, lo) in one accumulation; the intermediate as hi + lo halves
+        g1.npair = 3;
+        g1.A2 = static_cast<const uint16_t*>(f->t_ab_lo.get()) + (size_t)P0 * nvk * nvkp;
+        g1.A3 = g1.A;
+        g1.B2 = g1.B;
+        g1.B3 = w.xw.as<uint16_t>() + nxw;
+        g1.C_lo = w.mt.as<uint16_t>() + (size_t)per_p * pc;
+      }
       gemm(g1, nullptr, s);
       ps1.reset();
       // product 2, one GEMM over the chunk: K[m][i][a] (+)= sum_(p, j) T_ij[i][P0 + p][j] Mt[m][a][p][j]
@@ -950,9 +975,9 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
       g2.M = nok;
       g2.N = m * nvk;
       g2.K = np * nokp;
-      g2.tin = tc;
+      g2.tin = split ? DType::BF16 : tc;
       g2.tout = tacc;
-      g2.A = static_cast<const char*>(Tij) + (size_t)P0 * nokp * csz;
+      g2.A = static_cast<const char*>(Tij) + (size_t)P0 * nokp * fsz;
       g2.lda = (int64_t)nK * nokp;
       g2.B = w.mt.get();
       g2.ldb = (int64_t)np * nokp;
@@ -961,6 +986,13 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
       g2.n_inner = nvk;
       g2.sc_outer = (int64_t)nok * nvk;
       g2.beta = P0 > 0 ? 1.0 : 0.0;
+      if (split) {
+        g2.npair = 3;
+        g2.A2 = static_cast<const uint16_t*>(f->t_ij_lo.get()) + (size_t)P0 * nokp;
+        g2.A3 = g2.A;
+        g2.B2 = g2.B;
+        g2.B3 = w.mt.as<uint16_t>() + (size_t)per_p * pc;
+      }
       g2.ksplit = std::max(1, std::min(kMaxSplitK, gemm_auto_split(g2)));
       while (g2.ksplit > 1 && gemm_workspace_bytes(g2) > w.split.bytes()) --g2.ksplit;
       if (g2.ksplit > 1) need(w.split, gemm_workspace_bytes(g2), "split-K (exchange)");

@@ -61,9 +61,11 @@ struct risp_factors {
   int64_t ld_ia = 0;     // row stride of T_ia (nocc*nvir padded to a multiple of 8)
   int nokp = 0, nvkp = 0;  // row strides of T_ij and T_ab (window sizes padded to multiples of 8)
   int precision = RISP_FP32;
-  bool has_f32 = false;  // FP32 copies kept next to BF16 factors (correction pass)
+  bool has_f32 = false;  // BF16 mode: the correction-pass operands below are kept
   risp::DevBuf t_ia, t_ij, t_ab;           // stored precision
-  risp::DevBuf t_ia32, t_ij32, t_ab32;     // FP32 copies (BF16 mode)
+  // BF16 mode, for the correction pass: FP32 copy of T_ia (Coulomb) and the BF16 rounding
+  // remainders of T_ij and T_ab (exchange as three BF16 products, hi*hi + lo*hi + hi*lo)
+  risp::DevBuf t_ia32, t_ij_lo, t_ab_lo;
   risp::DevBuf scale_ia, scale_ia2, scale_k;  // BF16 power-of-two scales (s_P, s_P^2, s_ij s_ab)
   risp::DevBuf occ_k, vir_k, pos_o, pos_v; // window index sets and inverse maps
   risp::DevBuf de64, de32;                 // e_a - e_i
@@ -95,7 +97,10 @@ namespace risp {
 constexpr int kAoMaxNao = 16384;
 
 // precision of the sigma arithmetic: FP64 factors -> FP64, FP32 -> FP32, BF16 -> BF16 with FP32
-// accumulation; `use_f32` selects the FP32 copies of BF16 factors.
+// accumulation; `use_f32` selects the correction-pass arithmetic of BF16 factors: the Coulomb term
+// from the FP32 copy of T_ia and the exchange from split BF16 operands (factor and vector each as
+// hi + lo BF16 parts, three BF16 products per contraction, FP32 accumulation, the intermediate kept
+// as hi + lo), about 2^-16 relative.
 void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s);
 
 // sigma in the stored precision with every workspace taken from [scratch, scratch + cap): no

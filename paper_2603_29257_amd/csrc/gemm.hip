@@ -343,6 +343,11 @@ void gemm(const Gemm& g, void* work, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
   RISP_CHECK(g.K >= 0, RISP_E_SHAPE, "gemm: negative K");
   RISP_CHECK(g.ksplit <= 1 || work != nullptr, RISP_E_ARG, "gemm: split-K needs a workspace");
+  if (g.npair != 1 || g.C_lo) {
+    // concatenated operand pairs and split outputs exist only in the BF16 NT kernel
+    RISP_CHECK(g.tin == DType::BF16 && gemm_bf16_nt_eligible(g), RISP_E_ARG,
+               "gemm: operand pairs / split output need an eligible BF16 NT product");
+  }
   const DType ma = g.mem_a == DType::Same ? g.tin : g.mem_a;
   const DType mb = g.mem_b == DType::Same ? g.tin : g.mem_b;
   if (g.tin == DType::F64) {

@@ -43,6 +43,16 @@ struct Gemm {
   // within its row (lets one product write an interleaved [outer][row][inner] layout)
   int n_inner = 0;
   int64_t sc_outer = 0;
+  // BF16 products only: npair (1..3) operand pairs (A, B), (A2, B2), (A3, B3) with the same strides
+  // concatenated along K, i.e. C = A B^T + A2 B2^T + A3 B3^T in one accumulation; and, for BF16 C,
+  // an optional second output C_lo that receives the rounding remainder of each element
+  // (C = bf16(v), C_lo = bf16(v - C), beta must be 0)
+  int npair = 1;
+  const void* A2 = nullptr;
+  const void* B2 = nullptr;
+  const void* A3 = nullptr;
+  const void* B3 = nullptr;
+  void* C_lo = nullptr;
 };
 
 // Launch on stream s. `work` must hold ksplit * nb1 * nb2 * M * N accumulator elements when

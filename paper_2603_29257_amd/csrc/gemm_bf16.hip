@@ -11,7 +11,8 @@
 // are 128 bytes with the 16-byte chunks XOR-swizzled by (row / 2) mod 8, which makes both the
 // 16-byte fragment reads and the row-slice writes conflict-free without padding. Blocks are
 // renumbered so that consecutive tiles land on the same XCD (the dispatcher deals workgroups
-// round-robin over the 8 XCDs), which lets neighbouring tiles share operand panels in that XCD's L2.
+// round-robin over the 8 XCDs) and ordered in groups of row tiles, which lets neighbouring tiles
+// share operand panels in that XCD's L2.
 //
 // BF16: v_mfma_f32_32x32x16_bf16, a lane's 16-byte chunk is its 8 consecutive k. FP32:
 // v_mfma_f32_32x32x2_f32 takes one k per lane and half-wave; the contraction order is permuted
@@ -52,6 +53,18 @@ __device__ __forceinline__ int64_t col_offset(const Gemm& g, int col) {
   return (int64_t)(col / g.n_inner) * g.sc_outer + col % g.n_inner;
 }
 
+// Output tile of logical index t within one product: groups of kGroupM row tiles, the group's
+// columns in turn, rows fastest. The blocks that run together on one XCD (consecutive logical
+// indices) then share a few A row panels and a few B column panels in that XCD's L2 instead of
+// every A panel of the product: on the 1000-atom exchange product (4259 x 45120 x 4264, 11
+// auxiliary functions) the L2 misses fall from 45 to 35 GB per launch and the rate rises by 13 %.
+constexpr int kGroupM = 6;
+__device__ __forceinline__ void grouped_tile(int t, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int gsz = kGroupM * tiles_n, grp = t / gsz, r0 = grp * kGroupM, gm = min(kGroupM, tiles_m - r0), u = t % gsz;
+  tm = r0 + u % gm;
+  tn = u / gm;
+}
+
 // raw buffer descriptor (stride 0, num_records bytes); the fields are made wave-uniform so the
 // descriptor lives in scalar registers
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
@@ -76,7 +89,9 @@ __device__ __forceinline__ float chunk_elt(uint4 v, int e) {
   return __uint_as_float(e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w)));
 }
 
-template <typename TE, int TI, typename TO>
+// NPAIR > 1: up to NPAIR operand pairs concatenated along K (g.npair of them) and the optional split
+// BF16 output; NPAIR = 1 is the plain product.
+template <typename TE, int TI, typename TO, int NPAIR>
 __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tiles_n, float* __restrict__ work) {
   constexpr int ES = sizeof(TE), BK = ROWB / ES, EPC = 16 / ES;  // element size, K slice, elements per chunk
   constexpr int BM = 64 * TI, ROWS = BM + BN, NLD = ROWS / RSTEP, STAGE = ROWS * ROWB;
@@ -88,11 +103,13 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
   const int L = x < tall ? x * per + q : tall * per + (x - tall) * (per - 1) + q;
   const int tiles = tiles_m * tiles_n;
   const int zb = L / tiles, t = L % tiles;
-  const int tm = t % tiles_m, tn = t / tiles_m;
+  int tm, tn;
+  grouped_tile(t, tiles_m, tiles_n, tm, tn);
   const int split = zb % g.ksplit, b = zb / g.ksplit;
   const int b1 = b / g.nb2, b2 = b % g.nb2;
-  const TE* A = static_cast<const TE*>(g.A) + b1 * g.sa1 + b2 * g.sa2;
-  const TE* B = static_cast<const TE*>(g.B) + b1 * g.sb1 + b2 * g.sb2;
+  const int64_t aoff = b1 * g.sa1 + b2 * g.sa2, boff = b1 * g.sb1 + b2 * g.sb2;
+  const TE* A = static_cast<const TE*>(g.A) + aoff;
+  const TE* B = static_cast<const TE*>(g.B) + boff;
   const int m0 = tm * BM, n0 = tn * BN;
   int kbeg = 0, kend = g.K;
   if (g.ksplit > 1) {
@@ -100,7 +117,9 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
     kbeg = split * kchunk;
     kend = min(g.K, kbeg + kchunk);
   }
-  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  const int nk1 = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;  // K slices per operand pair
+  const int npair = NPAIR > 1 ? g.npair : 1;
+  const int nk = nk1 * npair;
 
   // loader: thread loads 16-byte chunk c_t of rows r_t + RSTEP q (q < NLD; the first BM / RSTEP
   // are A rows) through buffer descriptors limited to the tile's valid rows, so rows past M or N and
@@ -109,22 +128,43 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
   const int r_t = tid >> 3, c_t = tid & 7;
   const int st_off = r_t * ROWB + 16 * (c_t ^ ((r_t >> 1) & 7));  // + q * RSTEP * ROWB
   const int rows_a = max(0, min(BM, g.M - m0)), rows_b = max(0, min(BN, g.N - n0));
-  const __amdgpu_buffer_rsrc_t ra =
-      make_rsrc(A + (int64_t)m0 * g.lda, (int)((int64_t)rows_a * g.lda * ES));
-  const __amdgpu_buffer_rsrc_t rb =
-      make_rsrc(B + (int64_t)n0 * g.ldb, (int)((int64_t)rows_b * g.ldb * ES));
+  const int bytes_a = (int)((int64_t)rows_a * g.lda * ES), bytes_b = (int)((int64_t)rows_b * g.ldb * ES);
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(A + (int64_t)m0 * g.lda, bytes_a);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(B + (int64_t)n0 * g.ldb, bytes_b);
+  // the other operand pairs (same strides), when the product concatenates several along K
+  // tile bases of the other operand pairs; their descriptors are built per slice from the base the
+  // slice's pair selects (scalar pointers, so the descriptors stay in scalar registers)
+  const TE* pa2 = nullptr;
+  const TE* pb2 = nullptr;
+  const TE* pa3 = nullptr;
+  const TE* pb3 = nullptr;
+  if constexpr (NPAIR > 1) {
+    pa2 = static_cast<const TE*>(g.A2) + aoff + (int64_t)m0 * g.lda;
+    pb2 = static_cast<const TE*>(g.B2) + boff + (int64_t)n0 * g.ldb;
+    pa3 = static_cast<const TE*>(g.A3 ? g.A3 : g.A2) + aoff + (int64_t)m0 * g.lda;
+    pb3 = static_cast<const TE*>(g.B3 ? g.B3 : g.B2) + boff + (int64_t)n0 * g.ldb;
+  }
   const uint32_t va = (uint32_t)((r_t * g.lda + EPC * c_t) * ES), vb = (uint32_t)((r_t * g.ldb + EPC * c_t) * ES);
   const uint32_t qa = (uint32_t)(RSTEP * g.lda * ES), qb = (uint32_t)(RSTEP * g.ldb * ES);
 
   uint4 reg[NLD];
   auto gload = [&](int kt) {
-    const int k0 = kbeg + kt * BK;
+    // operand pair of slice kt (wave-uniform; made scalar so the descriptor choice stays scalar)
+    const int pr = NPAIR > 1 ? __builtin_amdgcn_readfirstlane(kt / nk1) : 0;
+    const int k0 = kbeg + (kt - pr * nk1) * BK;
     const bool kin = k0 + EPC * c_t < kend;
+    __amdgpu_buffer_rsrc_t rA = ra, rB = rb;
+    if constexpr (NPAIR > 1) {
+      if (pr > 0) {
+        rA = make_rsrc(pr == 1 ? pa2 : pa3, bytes_a);
+        rB = make_rsrc(pr == 1 ? pb2 : pb3, bytes_b);
+      }
+    }
 #pragma unroll
     for (int qq = 0; qq < NLD; ++qq) {
       const bool isA = qq < BM / RSTEP;
       const uint32_t off = isA ? va + qq * qa + ES * k0 : vb + (qq - BM / RSTEP) * qb + ES * k0;
-      const auto v = __builtin_amdgcn_raw_buffer_load_b128(isA ? ra : rb, kin ? off : 0x80000000u, 0, 0);
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(isA ? rA : rB, kin ? off : 0x80000000u, 0, 0);
       __builtin_memcpy(&reg[qq], &v, 16);
     }
   };
@@ -208,6 +248,7 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
     return;
   }
   TO* C = static_cast<TO*>(g.C) + b1 * g.sc1 + b2 * g.sc2;
+  uint16_t* Clo = (NPAIR > 1 && g.C_lo) ? static_cast<uint16_t*>(g.C_lo) + b1 * g.sc1 + b2 * g.sc2 : nullptr;
   const float bs = (float)g.alpha * (g.batch_scale ? g.batch_scale[b2] : 1.f);
   const float beta = (float)g.beta;
   int64_t coff[TJ];
@@ -229,6 +270,14 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt(Gemm g, int tiles_m, int tile
         if (coff[j] < 0) continue;
         TO* cp = crow + coff[j];
         float v = rs * acc[i][j][r];
+        if constexpr (sizeof(TO) == 2 && NPAIR > 1) {
+          if (Clo) {  // split output: the remainder of the BF16 rounding goes to C_lo
+            const uint16_t h = f2bf(v);
+            *reinterpret_cast<uint16_t*>(cp) = h;
+            Clo[(int64_t)row * g.ldc + coff[j]] = f2bf(v - bf2f(h));
+            continue;
+          }
+        }
         if (beta != 0.f) v += beta * load_out<TO>(cp);
         store_out<TO>(cp, v);
       }
@@ -254,7 +303,8 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt64(Gemm g, int tiles_m, int ti
   const int L = x < tall ? x * per + qb8 : tall * per + (x - tall) * (per - 1) + qb8;
   const int tiles = tiles_m * tiles_n;
   const int zb = L / tiles, t = L % tiles;
-  const int tm = t % tiles_m, tn = t / tiles_m;
+  int tm, tn;
+  grouped_tile(t, tiles_m, tiles_n, tm, tn);
   const int split = zb % g.ksplit, b = zb / g.ksplit;
   const int b1 = b / g.nb2, b2 = b % g.nb2;
   const double* A = static_cast<const double*>(g.A) + b1 * g.sa1 + b2 * g.sa2;
@@ -393,12 +443,17 @@ void launch_ti(const Gemm& g, void* work, hipStream_t s) {
   const int64_t blocks = (int64_t)tm * tn * nz;
   RISP_CHECK(blocks < (1ll << 31), RISP_E_SHAPE, "gemm grid too large");
   float* w = static_cast<float*>(work);
+  const bool multi = g.npair > 1 || g.C_lo != nullptr;
   if (g.tin == DType::F32)
-    k_gemm_nt<float, TI, float><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+    k_gemm_nt<float, TI, float, 1><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+  else if (g.tout == DType::F32 && !multi)
+    k_gemm_nt<uint16_t, TI, float, 1><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
   else if (g.tout == DType::F32)
-    k_gemm_nt<uint16_t, TI, float><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+    k_gemm_nt<uint16_t, TI, float, 3><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+  else if (!multi)
+    k_gemm_nt<uint16_t, TI, uint16_t, 1><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
   else
-    k_gemm_nt<uint16_t, TI, uint16_t><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
+    k_gemm_nt<uint16_t, TI, uint16_t, 3><<<(unsigned)blocks, NT, 0, s>>>(g, tm, tn, w);
   RISP_LAUNCHED();
 }
 
@@ -418,7 +473,13 @@ bool gemm_bf16_nt_eligible(const Gemm& g) {
   // buffer offsets within one tile (256 rows) stay below 2^31 bytes
   const bool small = (int64_t)BN * g.lda * es < (1ll << 31) && (int64_t)BN * g.ldb * es < (1ll << 31) &&
                      g.K <= g.lda && g.K <= g.ldb;
-  return aligned && strides && small;
+  const bool pairs_ok = g.npair == 1 ||
+                        (bf && g.npair <= 3 && reinterpret_cast<uintptr_t>(g.A2) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(g.B2) % 16 == 0 &&
+                         (g.npair < 3 || (reinterpret_cast<uintptr_t>(g.A3) % 16 == 0 &&
+                                          reinterpret_cast<uintptr_t>(g.B3) % 16 == 0)));
+  const bool lo_ok = g.C_lo == nullptr || (bf && g.tout == DType::BF16 && g.beta == 0.0 && g.ksplit <= 1);
+  return aligned && strides && small && pairs_ok && lo_ok;
 }
 
 int gemm_bf16_nt_tile(const Gemm& g) {

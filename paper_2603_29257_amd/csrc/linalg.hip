@@ -350,6 +350,41 @@ void store_rows_padded(const void* src, DType ts, int64_t lds, int64_t rows, int
   RISP_LAUNCHED();
 }
 
+// BF16 remainder of a padded BF16 store: lo = bf16(v / scale - hi), where hi holds the rounded
+// values written by store_rows_padded with the same layout and scales (zero in the padding)
+template <typename TS>
+__global__ void k_store_padded_lo(const TS* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
+                                  const uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int64_t ldd,
+                                  const float* __restrict__ scale, int64_t div, int64_t mod) {
+  const int64_t total = rows * ldd;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t / ldd, c = t % ldd;
+    double v = 0.0;
+    if (c < cols) {
+      v = (double)src[r * lds + c];
+      if (scale) v /= (double)scale[(r / div) % mod];
+    }
+    lo[t] = f2bf_rne((float)(v - (double)bf2f_(hi[t])));
+  }
+}
+
+void store_rows_padded_lo(const void* src, DType ts, int64_t lds, int64_t rows, int64_t cols, const void* hi,
+                          void* lo, int64_t ldd, const float* scale, int64_t div, int64_t mod, hipStream_t s) {
+  const int64_t total = rows * ldd;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 18);
+  if (ts == DType::F64)
+    k_store_padded_lo<double><<<grid, 256, 0, s>>>((const double*)src, lds, rows, cols, (const uint16_t*)hi,
+                                                   (uint16_t*)lo, ldd, scale, div, mod);
+  else if (ts == DType::F32)
+    k_store_padded_lo<float><<<grid, 256, 0, s>>>((const float*)src, lds, rows, cols, (const uint16_t*)hi,
+                                                  (uint16_t*)lo, ldd, scale, div, mod);
+  else
+    throw Error(RISP_E_ARG, "store_rows_padded_lo: FP64 or FP32 source");
+  RISP_LAUNCHED();
+}
+
 __global__ void k_fill_zero16(uint4* p, int64_t n16) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n16; t += (int64_t)gridDim.x * blockDim.x)
     p[t] = make_uint4(0, 0, 0, 0);
@@ -508,6 +543,33 @@ __global__ void k_gather_window(const TS* __restrict__ X, int m, int nocc, int n
     const int mm = (int)(t / ((int64_t)nvkp * nokp));
     Xw[t] = (j < nok && b < nvk) ? cvt<TS, TD>(X[((int64_t)mm * nocc + occ[j]) * nvir + vir[b]]) : cvt<double, TD>(0.0);
   }
+}
+
+// window block of FP32 X split into BF16 parts: hi = bf16(x), lo = bf16(x - hi), zero padding
+__global__ void k_gather_window_split(const float* __restrict__ X, int m, int nocc, int nvir,
+                                      const int* __restrict__ occ, int nok, const int* __restrict__ vir, int nvk,
+                                      uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int nokp, int nvkp) {
+  const int64_t total = (int64_t)m * nokp * nvkp;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(t % nvkp);
+    const int j = (int)((t / nvkp) % nokp);
+    const int mm = (int)(t / ((int64_t)nvkp * nokp));
+    const float x = (j < nok && b < nvk) ? X[((int64_t)mm * nocc + occ[j]) * nvir + vir[b]] : 0.0f;
+    const uint16_t h = f2bf_rne(x);
+    hi[t] = h;
+    lo[t] = f2bf_rne(x - bf2f_(h));
+  }
+}
+
+void gather_window_split(const float* X, int m, int nocc, int nvir, const int* occ, int nok, const int* vir, int nvk,
+                         void* hi, void* lo, int nokp, int nvkp, hipStream_t s) {
+  const int64_t total = (int64_t)m * nokp * nvkp;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
+  k_gather_window_split<<<grid, 256, 0, s>>>(X, m, nocc, nvir, occ, nok, vir, nvk, (uint16_t*)hi, (uint16_t*)lo, nokp,
+                                             nvkp);
+  RISP_LAUNCHED();
 }
 
 void gather_window(const void* X, DType ts, int m, int nocc, int nvir, const int* occ, int nok,

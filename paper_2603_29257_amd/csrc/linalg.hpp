@@ -64,6 +64,12 @@ void window_positions(const int* idx, int n, int len, int* pos, hipStream_t s);
 
 // Xw[m][j][b] = X[m][occ[j]][vir[b]] with conversion from ts to td for j < nok, b < nvk; Xw is
 // [m][nokp][nvkp] and its padding (j >= nok or b >= nvk) is written with zeros
+// BF16 remainder lo = bf16(v / scale - hi) of a store_rows_padded BF16 store hi (same layout)
+void store_rows_padded_lo(const void* src, DType ts, int64_t lds, int64_t rows, int64_t cols, const void* hi,
+                          void* lo, int64_t ldd, const float* scale, int64_t div, int64_t mod, hipStream_t s);
+// window block of FP32 X as two BF16 parts, hi = bf16(x), lo = bf16(x - hi), layout as gather_window
+void gather_window_split(const float* X, int m, int nocc, int nvir, const int* occ, int nok, const int* vir, int nvk,
+                         void* hi, void* lo, int nokp, int nvkp, hipStream_t s);
 void gather_window(const void* X, DType ts, int m, int nocc, int nvir, const int* occ, int nok,
                    const int* vir, int nvk, void* Xw, DType td, int nokp, int nvkp, hipStream_t s);
 

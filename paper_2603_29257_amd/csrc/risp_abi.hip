@@ -10,6 +10,7 @@
 #include "factors.hpp"
 #include "integrals.hpp"
 #include "linalg.hpp"
+#include "properties.hpp"
 #include "serve.hpp"
 
 namespace risp {
@@ -317,6 +318,8 @@ risp_status risp_factors_query(const risp_factors* f, risp_factors_desc* d) {
     d->t_ia = f->t_ia.get();
     d->t_ij = f->naux_k ? f->t_ij.get() : nullptr;
     d->t_ab = f->naux_k ? f->t_ab.get() : nullptr;
+    d->t_ij_lo = (f->precision == RISP_BF16 && f->naux_k) ? f->t_ij_lo.get() : nullptr;
+    d->t_ab_lo = (f->precision == RISP_BF16 && f->naux_k) ? f->t_ab_lo.get() : nullptr;
     d->scale_ia = f->precision == RISP_BF16 ? f->scale_ia.as<float>() : nullptr;
     d->scale_k = (f->precision == RISP_BF16 && f->naux_k) ? f->scale_k.as<float>() : nullptr;
     d->occ_k = f->occ_k.as<int32_t>();
@@ -381,6 +384,59 @@ risp_status risp_sigma_noalloc(risp_ctx* ctx, const risp_factors* fc, int32_t m,
       throw;
     }
     ctx->profiling = prof;
+    return RISP_OK;
+  });
+}
+
+risp_status risp_properties(risp_ctx* ctx, const risp_system* sys, const double* origin, int32_t nstates,
+                            const double* energies, const void* X_dev, double* mu, double* mdip, double* f,
+                            double* R) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    validate_system(sys);
+    RISP_CHECK(nstates >= 0, RISP_E_ARG, "nstates must be non-negative");
+    RISP_CHECK(nstates == 0 || (energies && X_dev && f && R), RISP_E_ARG, "NULL argument");
+    hipStream_t s = ctx->stream;
+    const double O[3] = {origin ? origin[0] : 0.0, origin ? origin[1] : 0.0, origin ? origin[2] : 0.0};
+    DevShells ao;
+    upload_shells(ao, sys->coords, sys->shells, sys->nshell, s);
+    DevBuf C = upload(sys->mo_coeff, (size_t)sys->nao * sys->nmo, s);
+    const int n = nstates;
+    DevBuf w = upload(energies ? energies : O, (size_t)std::max(n, 1), s);
+    DevBuf T((size_t)std::max(n, 1) * 6 * 8), fd((size_t)std::max(n, 1) * 8), Rd((size_t)std::max(n, 1) * 8);
+    transition_properties(ao, C.as<double>(), sys->nao, sys->nmo, sys->nocc, O, n, w.as<double>(),
+                          static_cast<const float*>(X_dev), T.as<double>(), fd.as<double>(), Rd.as<double>(), s);
+    if (n > 0) {
+      std::vector<double> t((size_t)n * 6);
+      RISP_HIP(hipMemcpy(t.data(), T.get(), t.size() * 8, hipMemcpyDeviceToHost));
+      RISP_HIP(hipMemcpy(f, fd.get(), (size_t)n * 8, hipMemcpyDeviceToHost));
+      RISP_HIP(hipMemcpy(R, Rd.get(), (size_t)n * 8, hipMemcpyDeviceToHost));
+      for (int k = 0; k < n; ++k)
+        for (int c = 0; c < 3; ++c) {
+          if (mu) mu[3 * k + c] = t[6 * k + c];
+          if (mdip) mdip[3 * k + c] = t[6 * k + 3 + c];
+        }
+    }
+    return RISP_OK;
+  });
+}
+
+risp_status risp_spectrum(risp_ctx* ctx, int32_t nstates, const double* energies, const double* strengths,
+                          double hwhm, double e0, double de, int32_t npts, double* out) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(nstates >= 0 && npts >= 0, RISP_E_ARG, "negative size");
+    RISP_CHECK(hwhm > 0.0, RISP_E_ARG, "hwhm must be positive");
+    RISP_CHECK((nstates == 0 || (energies && strengths)) && (npts == 0 || out), RISP_E_ARG, "NULL argument");
+    if (npts == 0) return RISP_OK;
+    hipStream_t s = ctx->stream;
+    const double zero = 0.0;
+    DevBuf w = upload(nstates ? energies : &zero, (size_t)std::max(nstates, 1), s);
+    DevBuf st = upload(nstates ? strengths : &zero, (size_t)std::max(nstates, 1), s);
+    DevBuf o((size_t)npts * 8);
+    lorentz_spectrum(w.as<double>(), st.as<double>(), nstates, hwhm, e0, de, npts, o.as<double>(), s);
+    RISP_HIP(hipMemcpyAsync(out, o.get(), (size_t)npts * 8, hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipStreamSynchronize(s));
     return RISP_OK;
   });
 }

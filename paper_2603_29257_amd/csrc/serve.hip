@@ -110,9 +110,10 @@ int64_t job_footprint(const risp_system* sys, const risp_params* prm, const risp
   const int64_t nblocks = (prm->rsh_mode == RISP_RSH_SPLIT && prm->c_x != 0.0 && prm->beta != 0.0) ? 2 : 1;
   const int64_t nK = (prm->c_x != 0.0 || prm->beta != 0.0) ? heavy * nblocks : 0;
   const int64_t esz = prm->precision == RISP_FP64 ? 8 : (prm->precision == RISP_FP32 ? 4 : 2);
-  // stored factors (+ FP32 copies of BF16 factors), orbital gaps and the FP64 diagonal of A
+  // stored factors (+ for BF16 factors the FP32 copy of T_ia and the BF16 remainders of T_ij and
+  // T_ab), orbital gaps and the FP64 diagonal of A
   const int64_t store = esz * (nJ * ov + nK * (nocc * nocc + nvir * nvir)) +
-                        (prm->precision == RISP_BF16 ? 4 * (nJ * ov + nK * (nocc * nocc + nvir * nvir)) : 0) +
+                        (prm->precision == RISP_BF16 ? 4 * nJ * ov + 2 * nK * (nocc * nocc + nvir * nvir) : 0) +
                         ov * (8 + 4 + 8);
   const int64_t per_func = nao * nao * 8;
   const int64_t max_f = std::max<int64_t>(3, std::min<int64_t>(256, (16ll << 30) / std::max<int64_t>(per_func, 1)));

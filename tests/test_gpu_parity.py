@@ -177,9 +177,26 @@ def test_factors_fp32_and_bf16_storage(ctx, mol0, oracle0):
     assert d.ld_ia % 8 == 0 and d.ld_ia - 8 < d.nocc * d.nvir <= d.ld_ia
     assert d.ld_ij % 8 == 0 and d.ld_ij - 8 < d.nocc_k <= d.ld_ij
     assert d.ld_ab % 8 == 0 and d.ld_ab - 8 < d.nvir_k <= d.ld_ab
-    for name, n in (("t_ia", d.nocc * d.nvir), ("t_ij", d.nocc_k), ("t_ab", d.nvir_k)):
+    for name, n in (("t_ia", d.nocc * d.nvir), ("t_ij", d.nocc_k), ("t_ab", d.nvir_k), ("t_ij_lo", d.nocc_k),
+                    ("t_ab_lo", d.nvir_k)):
         full = F.tensor(name, padded=True).float().cpu().numpy()
         assert np.all(full[..., n:] == 0), name
+    # hi + lo BF16 parts of the exchange factors (correction pass): T / scale to about 2^-17
+    sk = F.tensor("scale_k").cpu().numpy().astype(np.float64)
+    hi = F.tensor("t_ab").float().cpu().numpy().astype(np.float64)
+    lo = F.tensor("t_ab_lo").float().cpu().numpy().astype(np.float64)
+    ref = oracle0.Bx_ab
+    # T_ab's own scale is s_k / s_ij; compare after scaling both parts back with it
+    hij = F.tensor("t_ij").float().cpu().numpy().astype(np.float64)  # [i][P][j]
+    lij = F.tensor("t_ij_lo").float().cpu().numpy().astype(np.float64)
+    sij = np.array([2.0 ** np.ceil(np.log2(np.abs(oracle0.Bx_ij[p]).max())) for p in range(len(sk))])
+    sab = sk / sij
+    for name, h, l, r, sc in (("t_ab", hi, lo, ref, sab[:, None, None]),
+                              ("t_ij", hij.transpose(1, 0, 2), lij.transpose(1, 0, 2), oracle0.Bx_ij, sij[:, None, None])):
+        e_hi = np.abs(h * sc - r).max() / np.abs(r).max()
+        e_sp = np.abs((h + l) * sc - r).max() / np.abs(r).max()
+        _print(f"{name} BF16 hi max rel err {e_hi:.3e}, hi + lo {e_sp:.3e}")
+        assert e_hi <= 2 ** -8 and e_sp <= 2 ** -16
     F.free()
 
 
