@@ -104,7 +104,9 @@ typedef struct {
                               occupied / window-virtual orbitals as needed; 0 = a quarter of the
                               free device memory, between 1 and 64 GiB */
   int32_t j_mode;     /* RISP_J_*: how the Coulomb term of sigma is formed */
-  int32_t reserved;   /* 0 */
+  int32_t full_tddft; /* nonzero: also build the windowed exchange factor over (i, a) pairs that
+                         full TDDFT-risp needs (Fig. tensors_shape, T_ia^P'); FP64/FP32 factors,
+                         combined exchange reading, stored-factor Coulomb route; 0 = TDA only */
 } risp_params;
 
 typedef struct {
@@ -291,6 +293,30 @@ risp_status risp_sigma(risp_ctx *ctx, const risp_factors *f, int32_t m, const vo
  * threads, two contexts) race, so serialise them. Stream-ordered, no synchronisation. */
 risp_status risp_sigma_noalloc(risp_ctx *ctx, const risp_factors *f, int32_t m, const void *X_dev,
                                void *sigma_dev, int32_t dtype);
+
+/* Products of full TDDFT-risp (eq. hessian, XC kernel dropped) for m vectors V: P = (A + B) V and
+ * M = (A - B) V, with A + B = de + 4 (ia|jb) - [window] ((ij|J^|ab) + (ib|J^|ja)) and
+ * A - B = de - [window] ((ij|J^|ab) - (ib|J^|ja)) (the Coulomb part of A + B is 4 (ia|jb) so that A
+ * is that of eq. TDA-risp; the printed eq. hessian shows 2). V_dev, P_dev, M_dev: device
+ * [m][nocc][nvir] in the factor precision (dtype RISP_FP64 or RISP_FP32); factors built with
+ * full_tddft. Synchronises the factors' stream (it allocates the exchange intermediate). */
+risp_status risp_sigma_full(risp_ctx *ctx, const risp_factors *f, int32_t m, const void *V_dev, void *P_dev,
+                            void *M_dev, int32_t dtype);
+
+/* Full TDDFT-risp (eq. tddft with the matrices of eq. hessian, XC kernel dropped, the same RI
+ * factors, window and exchange operator as TDA-risp plus the windowed exchange factor over (i, a)
+ * pairs): the lowest nstates excitation energies Omega and amplitudes X + Y, X - Y with
+ * (X + Y).(X - Y) = 1. Needs factors built with risp_params.full_tddft (FP64 or FP32 storage).
+ * Davidson-like solver on one subspace for (A + B) and (A - B) (section on Davidson settings):
+ * FP64 projected matrices, A - B = L L^T (Cholesky), the symmetric problem L^T (A + B) L c =
+ * Omega^2 c by the same subspace eigensolver, both residuals preconditioned with 1/(Omega - diag A)
+ * and added to the subspace; restarts rebuild the subspace from the current X + Y and X - Y.
+ * opts: nstates (<= 32), block, max_space, max_iter, tol (both residual norms per state) and
+ * RISP_DAV_VERBOSE; nx0 must be 0. energies: host [nstates]; xpy, xmy: host [nstates][nocc*nvir]
+ * or NULL. Returns RISP_E_NOTCONV (results written) when max_iter is reached and RISP_E_STATE when
+ * the projected A - B is not positive definite (unstable ground state). */
+risp_status risp_davidson_full(risp_ctx *ctx, const risp_factors *f, const risp_dav_opts *opts,
+                               double *energies, float *xpy, float *xmy, risp_dav_info *info);
 
 /* Transition properties of nstates excited states (eq. oscillator_strength, eq. rotator_strength,
  * eq. transition and eq. transition_magnetic in the dipole-length form with TDA amplitudes, Y = 0):

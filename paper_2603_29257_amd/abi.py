@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 EXPORTS = ("risp_last_error", "risp_ctx_create", "risp_ctx_destroy", "risp_ctx_profile", "risp_select_aux", "risp_window",
            "risp_screen", "risp_int2c", "risp_int3c", "risp_build_factors", "risp_factors_query",
-           "risp_factors_free", "risp_sigma", "risp_sigma_noalloc", "risp_properties", "risp_spectrum", "risp_davidson", "risp_serve_config", "risp_job_footprint",
+           "risp_factors_free", "risp_sigma", "risp_sigma_noalloc", "risp_davidson_full", "risp_properties", "risp_spectrum", "risp_davidson", "risp_serve_config", "risp_job_footprint",
            "risp_submit", "risp_poll", "risp_serve_stats_get", "risp_device_usage")
 
 
@@ -53,7 +53,7 @@ class ParamsC(C.Structure):
                 ("theta", C.c_double), ("schwarz_tau", C.c_double), ("rsh_mode", C.c_int32),
                 ("window_mode", C.c_int32), ("precision", C.c_int32), ("h_in_aux", C.c_int32),
                 ("bf16_scale", C.c_int32), ("build_chunk_kib", C.c_int32), ("j_mode", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("full_tddft", C.c_int32)]
 
 
 class DavOptsC(C.Structure):
@@ -129,6 +129,8 @@ def load_library(path: str = LIBPATH):
         "risp_factors_free": [vp],
         "risp_sigma": [vp, vp, i32, vp, vp, i32],
         "risp_sigma_noalloc": [vp, vp, i32, vp, vp, i32],
+        "risp_davidson_full": [vp, vp, P(DavOptsC), P(dbl), P(C.c_float), P(C.c_float), P(DavInfoC)],
+        "risp_sigma_full": [vp, vp, i32, vp, vp, vp, i32],
         "risp_properties": [vp, P(SystemC), P(dbl), i32, P(dbl), vp, P(dbl), P(dbl), P(dbl), P(dbl)],
         "risp_spectrum": [vp, i32, P(dbl), P(dbl), dbl, dbl, dbl, i32, P(dbl)],
         "risp_davidson": [vp, vp, P(DavOptsC), P(dbl), P(C.c_float), P(DavInfoC)],
@@ -175,11 +177,12 @@ class Params:
     bf16_scale: bool = True
     build_chunk_kib: int = 0
     j_mode: int = 0  # J_MO or J_AO_DIRECT
+    full_tddft: bool = False  # also build the exchange factor over (i, a) for full TDDFT-risp
 
     def c(self):
         return ParamsC(self.c_x, self.beta, self.omega, self.window_ev, self.theta, self.schwarz_tau,
                        self.rsh_mode, self.window_mode, self.precision, int(self.h_in_aux),
-                       int(self.bf16_scale), int(self.build_chunk_kib), int(self.j_mode), 0)
+                       int(self.bf16_scale), int(self.build_chunk_kib), int(self.j_mode), int(self.full_tddft))
 
 
 def device_usage(reset_peak=False):
@@ -504,6 +507,46 @@ class Context:
         st = ServeStatsC()
         _check(_LIB.risp_serve_stats_get(self.handle, C.byref(st)))
         return {k: getattr(st, k) for k, _ in ServeStatsC._fields_ if k != "reserved"}
+
+    def sigma_full(self, F: Factors, V):
+        """(A + B) V and (A - B) V (full TDDFT-risp) for a device tensor V [m][nocc][nvir] in the factor
+        precision; the factors must have been built with Params(full_tddft=True)."""
+        import torch
+        want = torch.float64 if F.desc.precision == FP64 else torch.float32
+        if V.dtype != want or V.device != self.device or not V.is_contiguous():
+            raise ValueError(f"V must be a contiguous {want} tensor on {self.device}")
+        if V.dim() != 3 or V.shape[1] != F.nocc or V.shape[2] != F.nvir:
+            raise ValueError("V must have shape [m, nocc, nvir]")
+        P, M = torch.empty_like(V), torch.empty_like(V)
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        _check(_LIB.risp_sigma_full(self.handle, F.handle, V.shape[0], C.c_void_p(V.data_ptr()),
+                                    C.c_void_p(P.data_ptr()), C.c_void_p(M.data_ptr()),
+                                    FP64 if want == torch.float64 else FP32))
+        cur.wait_stream(self.stream)
+        return P, M
+
+    def davidson_full(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, verbose=False,
+                      want_vectors=True, allow_notconv=False):
+        """Full TDDFT-risp: lowest excitation energies and X + Y, X - Y [nstates][nocc*nvir] (host)."""
+        ov = F.nocc * F.nvir
+        e = np.zeros(nstates)
+        xp = np.zeros((nstates, ov), np.float32) if want_vectors else None
+        xm = np.zeros((nstates, ov), np.float32) if want_vectors else None
+        o = DavOptsC(nstates, block, max_space, max_iter, tol, 0, 0, 0.0, 0, DAV_VERBOSE if verbose else 0, None, 0, 0)
+        info = DavInfoC()
+        import torch
+        torch.cuda.current_stream(self.device).synchronize()
+        rc = _LIB.risp_davidson_full(self.handle, F.handle, C.byref(o), _ptr(e, C.c_double),
+                                     None if xp is None else _ptr(xp, C.c_float),
+                                     None if xm is None else _ptr(xm, C.c_float), C.byref(info))
+        if rc < 0 and not (allow_notconv and rc == RISP_E_NOTCONV):
+            _check(rc)
+        n = min(256, info.iters)
+        di = DavInfo(info.iters, info.restarts, info.sigma_vectors, bool(info.converged), 0, 0, info.t_build,
+                     info.t_sigma, info.t_subspace, 0.0, 0.0, info.sigma_flops, 0.0, info.hbm_bytes,
+                     list(info.resid_hist[:n]))
+        return e, xp, xm, di
 
     def davidson(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, correction_pass=True,
                  x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0, verbose=False,

@@ -564,3 +564,378 @@ void davidson(risp_factors* f, const DavOptions& o, const SigmaFn& sigma_fn, Dav
 }
 
 }  // namespace risp
+
+// ---------------------------------------------------------------------------------------------
+// full TDDFT-risp
+// ---------------------------------------------------------------------------------------------
+namespace risp {
+
+namespace {
+
+// A[r][c] *= sc[c] for r < rows, c < cols (row stride ld)
+__global__ void k_scale_cols(double* A, int rows, int cols, int ld, const double* sc) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * cols) return;
+  const int r = (int)(t / cols), c = (int)(t % cols);
+  A[(int64_t)r * ld + c] *= sc[c];
+}
+
+}  // namespace
+
+void davidson_full(risp_factors* f, const DavOptions& o, FullResult& res) {
+  hipStream_t s = f->stream;
+  const int64_t ov = (int64_t)f->nocc * f->nvir;
+  const bool fp64 = f->precision == RISP_FP64;
+  const DType tvec = fp64 ? DType::F64 : DType::F32;
+  const size_t vsz = fp64 ? 8 : 4;
+  const int n = o.nstates;
+  RISP_CHECK(n > 0 && n <= ov && 2 * n <= 64, RISP_E_ARG, "full TDDFT: 1 <= nstates <= 32 and <= nocc*nvir");
+  RISP_CHECK(o.tol > 0.0, RISP_E_ARG, "tol must be positive");
+  RISP_CHECK(ov < (1ll << 31), RISP_E_SHAPE, "nocc*nvir too large");
+  const int blk = (int)std::min<int64_t>(std::max(n, o.block > 0 ? o.block : std::min(2 * n, 30)), ov);
+  RISP_CHECK(blk <= 64, RISP_E_ARG, "block is limited to 64 trial vectors");
+  const int nnew = 2 * n;  // corrections per iteration at most (two per state)
+  const int max_space = (int)std::min<int64_t>(o.max_space > 0 ? o.max_space : std::max(8 * blk, 4 * nnew), ov);
+  RISP_CHECK(max_space >= std::max(blk, nnew), RISP_E_ARG, "max_space too small");
+  const int cap = max_space + nnew;
+  RISP_CHECK(cap <= 1024, RISP_E_ARG, "max_space too large for the subspace solver");
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  const int wmax = std::max(blk, nnew);
+  DevBuf V((size_t)cap * ov * vsz), WP((size_t)cap * ov * vsz), WM((size_t)cap * ov * vsz);
+  DevBuf Pm((size_t)cap * cap * 8), Mm((size_t)cap * cap * 8), Hn((size_t)cap * wmax * 8);
+  DevBuf split((size_t)512 * cap * wmax * 8);
+  DevBuf L((size_t)cap * cap * 8), Li((size_t)cap * cap * 8), T1((size_t)cap * cap * 8), Sm((size_t)cap * cap * 8);
+  DevBuf Zc((size_t)cap * cap * 8), theta((size_t)cap * 8), eigws(subspace_eig_workspace(cap, n));
+  DevBuf Ac((size_t)cap * n * 8), Bc((size_t)cap * n * 8), om((size_t)n * 8), sc1((size_t)n * 8), sc2((size_t)n * 8);
+  res.XpY.alloc((size_t)n * ov * 8);
+  res.XmY.alloc((size_t)n * ov * 8);
+  DevBuf R1((size_t)n * ov * 8), R2((size_t)n * ov * 8), T((size_t)nnew * ov * 8), T2((size_t)nnew * ov * 8);
+  DevBuf Cmix((size_t)cap * nnew * 8), G(64 * 64 * 8), Cf(64 * 64 * 8), kept(sizeof(int)), src((size_t)nnew * sizeof(int));
+  const int nblk = (int)std::min<int64_t>(64, std::max<int64_t>(1, ov / 4096));
+  DevBuf partial((size_t)nnew * nblk * 8), norms((size_t)nnew * 8);
+  const double* dg = f->diag64.get() ? f->diag64.as<double>() : f->de64.as<double>();
+  auto vrow = [&](DevBuf& b, int r) { return static_cast<char*>(b.get()) + (size_t)r * ov * vsz; };
+
+  auto products = [&](int r0, int nn) {
+    RISP_HIP(hipStreamSynchronize(s));
+    Timer t;
+    sigma_full(f, nn, vrow(V, r0), vrow(WP, r0), vrow(WM, r0), s);
+    RISP_HIP(hipStreamSynchronize(s));
+    res.t_sigma += t.sec();
+    res.sigma_vectors += nn;
+    const double nK = f->naux_k, no = f->nok, nv = f->nvk;
+    res.sigma_flops += sigma_flops(f, nn) + 4.0 * (double)ov * f->naux_j * nn + 4.0 * nK * no * no * nv * nn;
+  };
+  // columns [n0, n0 + nn) of Msub = V^T W for rows [0, nall)
+  auto update = [&](DevBuf& Msub, DevBuf& W, int nall, int n0, int nn) {
+    Gemm g;
+    g.M = nall;
+    g.N = nn;
+    g.K = (int)ov;
+    g.tin = g.tout = DType::F64;
+    g.mem_a = tvec;
+    g.mem_b = tvec;
+    g.A = V.get();
+    g.lda = ov;
+    g.B = vrow(W, n0);
+    g.ldb = ov;
+    g.C = Hn.get();
+    g.ldc = nn;
+    g.ksplit = std::min(512, gemm_auto_split(g));
+    gemm(g, split.get(), s);
+    k_sym_update<<<ceil_div((int64_t)nall * nn, 256), 256, 0, s>>>(Msub.as<double>(), cap, Hn.as<double>(), nall, n0,
+                                                                   nn);
+    RISP_LAUNCHED();
+  };
+  // out [k][ov] (FP64) = alpha Cm^T Vsrc + beta out, Cm [nsub][ldcm] FP64
+  auto combine = [&](const double* Cm, int ldcm, int nsub, int k, const void* Vsrc, double* out, double alpha,
+                     double beta) {
+    Gemm g;
+    g.M = k;
+    g.N = (int)ov;
+    g.K = nsub;
+    g.tin = g.tout = DType::F64;
+    g.mem_a = DType::F64;
+    g.mem_b = tvec;
+    g.A = Cm;
+    g.lda = ldcm;
+    g.a_kc = false;
+    g.B = Vsrc;
+    g.ldb = ov;
+    g.b_kc = false;
+    g.C = out;
+    g.ldc = ov;
+    g.alpha = alpha;
+    g.beta = beta;
+    gemm(g, nullptr, s);
+  };
+  auto row_norms = [&](const double* Rr, int k, std::vector<double>& out) {
+    k_row_sumsq<<<dim3(nblk, k), 256, 0, s>>>(Rr, ov, partial.as<double>());
+    RISP_LAUNCHED();
+    k_finish_norms<<<ceil_div(k, 64), 64, 0, s>>>(partial.as<double>(), nblk, k, norms.as<double>());
+    RISP_LAUNCHED();
+    out.assign(k, 0.0);
+    RISP_HIP(hipMemcpyAsync(out.data(), norms.get(), k * 8, hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipStreamSynchronize(s));
+  };
+  // orthonormalise the nt FP64 rows of B within the block (coefficient-space Gram-Schmidt, twice)
+  auto orth = [&](DevBuf& B, int nt, bool unit_ref) {
+    int nk = nt;
+    for (int pass = 0; pass < 2 && nk > 0; ++pass) {
+      Gemm g;
+      g.M = nk;
+      g.N = nk;
+      g.K = (int)ov;
+      g.tin = g.tout = DType::F64;
+      g.A = B.get();
+      g.lda = ov;
+      g.B = B.get();
+      g.ldb = ov;
+      g.C = G.get();
+      g.ldc = nk;
+      g.ksplit = std::min(512, gemm_auto_split(g));
+      gemm(g, split.get(), s);
+      k_block_mgs<<<1, 64, 0, s>>>(G.as<double>(), nk, fp64 ? 1e-6 : 1e-5, (unit_ref || pass > 0) ? 1 : 0,
+                                    Cf.as<double>(), kept.as<int>());
+      RISP_LAUNCHED();
+      int h = 0;
+      RISP_HIP(hipMemcpyAsync(&h, kept.get(), sizeof(int), hipMemcpyDeviceToHost, s));
+      RISP_HIP(hipStreamSynchronize(s));
+      if (h == 0) return 0;
+      Gemm c;  // T2 = Cf B ; B <- T2
+      c.M = h;
+      c.N = (int)ov;
+      c.K = nk;
+      c.tin = c.tout = DType::F64;
+      c.A = Cf.get();
+      c.lda = nk;
+      c.B = B.get();
+      c.ldb = ov;
+      c.b_kc = false;
+      c.C = T2.get();
+      c.ldc = ov;
+      gemm(c, nullptr, s);
+      RISP_HIP(hipMemcpyAsync(B.get(), T2.get(), (size_t)h * ov * 8, hipMemcpyDeviceToDevice, s));
+      nk = h;
+    }
+    return nk;
+  };
+  // project the nt FP64 rows of B off V[0:nsub] (classical Gram-Schmidt, two passes)
+  auto project = [&](DevBuf& B, int nsub, int nt) {
+    for (int pass = 0; pass < 2 && nsub > 0; ++pass) {
+      Gemm g;  // Cmix[r][t] = V[r] . B[t]
+      g.M = nsub;
+      g.N = nt;
+      g.K = (int)ov;
+      g.tin = g.tout = DType::F64;
+      g.mem_a = tvec;
+      g.mem_b = DType::F64;
+      g.A = V.get();
+      g.lda = ov;
+      g.B = B.get();
+      g.ldb = ov;
+      g.C = Cmix.get();
+      g.ldc = nt;
+      g.ksplit = std::min(512, gemm_auto_split(g));
+      gemm(g, split.get(), s);
+      combine(Cmix.as<double>(), nt, nsub, nt, V.get(), B.as<double>(), -1.0, 1.0);
+    }
+  };
+  auto store = [&](DevBuf& B, int r0, int nn) {
+    if (fp64)
+      k_store_rows<double><<<grid_for((int64_t)nn * ov), 256, 0, s>>>(B.as<double>(), (int64_t)nn * ov,
+                                                                      reinterpret_cast<double*>(vrow(V, r0)));
+    else
+      k_store_rows<float><<<grid_for((int64_t)nn * ov), 256, 0, s>>>(B.as<double>(), (int64_t)nn * ov,
+                                                                     reinterpret_cast<float*>(vrow(V, r0)));
+    RISP_LAUNCHED();
+  };
+
+  // ---- guess: unit vectors at the lowest diagonal elements of A, ties by (i, a) ----
+  {
+    std::vector<double> d(ov);
+    RISP_HIP(hipMemcpyAsync(d.data(), dg, ov * 8, hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipStreamSynchronize(s));
+    std::vector<int> idx(ov);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::partial_sort(idx.begin(), idx.begin() + blk, idx.end(),
+                      [&](int a, int b) { return d[a] < d[b] || (d[a] == d[b] && a < b); });
+    DevBuf srcg((size_t)blk * sizeof(int));
+    RISP_HIP(hipMemcpyAsync(srcg.get(), idx.data(), blk * sizeof(int), hipMemcpyHostToDevice, s));
+    RISP_HIP(hipMemsetAsync(V.get(), 0, (size_t)blk * ov * vsz, s));
+    if (fp64) k_unit_rows<double><<<1, 64, 0, s>>>(V.as<double>(), ov, srcg.as<int>(), blk);
+    else k_unit_rows<float><<<1, 64, 0, s>>>(V.as<float>(), ov, srcg.as<int>(), blk);
+    RISP_LAUNCHED();
+    RISP_HIP(hipStreamSynchronize(s));
+  }
+  int nsub = blk;
+  products(0, nsub);
+  update(Pm, WP, nsub, 0, nsub);
+  update(Mm, WM, nsub, 0, nsub);
+
+  std::vector<double> hth, hom(n), r1, r2;
+  for (int it = 1;; ++it) {
+    Timer tsub;
+    const int k = nsub, nw = std::min(n, k);
+    // Mm = L L^T, S = L^T Pm L, S c = Omega^2 c
+    k_copy_sub<<<ceil_div((int64_t)k * k, 256), 256, 0, s>>>(Mm.as<double>(), cap, k, L.as<double>(), k);
+    RISP_LAUNCHED();
+    try {
+      cholesky(L.as<double>(), k, s);
+    } catch (const Error&) {
+      throw Error(RISP_E_STATE, "full TDDFT: the projected A - B is not positive definite (unstable ground state)");
+    }
+    tri_inverse(L.as<double>(), Li.as<double>(), k, s);
+    {
+      Gemm g;  // T1 = Pm L
+      g.M = k;
+      g.N = k;
+      g.K = k;
+      g.tin = g.tout = DType::F64;
+      g.A = Pm.get();
+      g.lda = cap;
+      g.B = L.get();  // B[j][t] = L[t][j]
+      g.ldb = k;
+      g.b_kc = false;
+      g.C = T1.get();
+      g.ldc = k;
+      gemm(g, nullptr, s);
+      Gemm h;  // S = L^T T1
+      h.M = k;
+      h.N = k;
+      h.K = k;
+      h.tin = h.tout = DType::F64;
+      h.A = L.get();  // A[i][t] = L[t][i]
+      h.lda = k;
+      h.a_kc = false;
+      h.B = T1.get();  // B[j][t] = T1[t][j]
+      h.ldb = k;
+      h.b_kc = false;
+      h.C = Sm.get();
+      h.ldc = k;
+      gemm(h, nullptr, s);
+    }
+    subspace_eig(Sm.as<double>(), k, k, nw, theta.as<double>(), Zc.as<double>(), eigws.as<double>(), s);
+    hth.assign(nw, 0.0);
+    RISP_HIP(hipMemcpyAsync(hth.data(), theta.get(), nw * 8, hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipStreamSynchronize(s));
+    std::vector<double> h1(nw), h2(nw);
+    for (int q = 0; q < nw; ++q) {
+      RISP_CHECK(hth[q] > 0.0, RISP_E_STATE, "full TDDFT: non-positive Omega^2 in the subspace");
+      hom[q] = std::sqrt(hth[q]);
+      h1[q] = 1.0 / std::sqrt(hom[q]);
+      h2[q] = std::sqrt(hom[q]);
+    }
+    RISP_HIP(hipMemcpyAsync(om.get(), hom.data(), nw * 8, hipMemcpyHostToDevice, s));
+    RISP_HIP(hipMemcpyAsync(sc1.get(), h1.data(), nw * 8, hipMemcpyHostToDevice, s));
+    RISP_HIP(hipMemcpyAsync(sc2.get(), h2.data(), nw * 8, hipMemcpyHostToDevice, s));
+    {
+      Gemm a;  // Ac[s][q] = sum_t L[s][t] c[t][q]
+      a.M = k;
+      a.N = nw;
+      a.K = k;
+      a.tin = a.tout = DType::F64;
+      a.A = L.get();
+      a.lda = k;
+      a.B = Zc.get();  // B[q][t] = Z[t][q]
+      a.ldb = k;
+      a.b_kc = false;
+      a.C = Ac.get();
+      a.ldc = nw;
+      gemm(a, nullptr, s);
+      Gemm b = a;  // Bc[s][q] = sum_t Li[t][s] c[t][q]
+      b.A = Li.get();
+      b.a_kc = false;
+      b.C = Bc.get();
+      gemm(b, nullptr, s);
+      k_scale_cols<<<ceil_div((int64_t)k * nw, 256), 256, 0, s>>>(Ac.as<double>(), k, nw, nw, sc1.as<double>());
+      RISP_LAUNCHED();
+      k_scale_cols<<<ceil_div((int64_t)k * nw, 256), 256, 0, s>>>(Bc.as<double>(), k, nw, nw, sc2.as<double>());
+      RISP_LAUNCHED();
+    }
+    double* xp = res.XpY.as<double>();
+    double* xm = res.XmY.as<double>();
+    combine(Ac.as<double>(), nw, k, nw, V.get(), xp, 1.0, 0.0);
+    combine(Bc.as<double>(), nw, k, nw, V.get(), xm, 1.0, 0.0);
+    combine(Ac.as<double>(), nw, k, nw, WP.get(), R1.as<double>(), 1.0, 0.0);
+    combine(Bc.as<double>(), nw, k, nw, WM.get(), R2.as<double>(), 1.0, 0.0);
+    k_residual<<<grid_for((int64_t)nw * ov), 256, 0, s>>>(R1.as<double>(), xm, om.as<double>(), nw, ov);
+    RISP_LAUNCHED();
+    k_residual<<<grid_for((int64_t)nw * ov), 256, 0, s>>>(R2.as<double>(), xp, om.as<double>(), nw, ov);
+    RISP_LAUNCHED();
+    row_norms(R1.as<double>(), nw, r1);
+    row_norms(R2.as<double>(), nw, r2);
+    res.iters = it;
+    res.omega.assign(hom.begin(), hom.begin() + nw);
+    double rmax = 0.0;
+    std::vector<int> todo;
+    for (int q = 0; q < nw; ++q) {
+      rmax = std::max(rmax, std::max(r1[q], r2[q]));
+      if (std::max(r1[q], r2[q]) >= o.tol) todo.push_back(q);
+    }
+    res.resid_hist.push_back(rmax);
+    if (o.log_tag) {
+      std::fprintf(stderr, "risp davidson %s: iteration %d, subspace %d, max residual %.3e\n", o.log_tag, it, nsub,
+                   rmax);
+      std::fflush(stderr);
+    }
+    if (nw >= n && todo.empty()) {
+      res.converged = true;
+      res.t_subspace += tsub.sec();
+      break;
+    }
+    if (it >= max_iter) {
+      res.t_subspace += tsub.sec();
+      break;
+    }
+    // corrections t = r / (Omega - diag A) for both residuals of the unconverged states
+    const int nq = (int)todo.size();
+    RISP_HIP(hipMemcpyAsync(src.get(), todo.data(), nq * sizeof(int), hipMemcpyHostToDevice, s));
+    k_precond<<<grid_for((int64_t)nq * ov), 256, 0, s>>>(R1.as<double>(), om.as<double>(), dg, src.as<int>(), nq, ov,
+                                                         T.as<double>());
+    RISP_LAUNCHED();
+    k_precond<<<grid_for((int64_t)nq * ov), 256, 0, s>>>(R2.as<double>(), om.as<double>(), dg, src.as<int>(), nq, ov,
+                                                         T.as<double>() + (size_t)nq * ov);
+    RISP_LAUNCHED();
+    int nt = 2 * nq;
+    {
+      std::vector<double> tn;
+      row_norms(T.as<double>(), nt, tn);
+      RISP_HIP(hipMemcpyAsync(norms.get(), tn.data(), nt * 8, hipMemcpyHostToDevice, s));
+      k_scale_rows<<<grid_for((int64_t)nt * ov), 256, 0, s>>>(T.as<double>(), nt, ov, norms.as<double>());
+      RISP_LAUNCHED();
+    }
+    if (nsub + nt > max_space) {
+      // restart: the subspace becomes X + Y and X - Y of the current states, products recomputed
+      DevBuf Rb((size_t)2 * nw * ov * 8);
+      RISP_HIP(hipMemcpyAsync(Rb.get(), xp, (size_t)nw * ov * 8, hipMemcpyDeviceToDevice, s));
+      RISP_HIP(hipMemcpyAsync(Rb.as<double>() + (size_t)nw * ov, xm, (size_t)nw * ov * 8, hipMemcpyDeviceToDevice, s));
+      // orthonormalise through T2 (which orth uses as its product buffer): copy in, orthonormalise, store
+      DevBuf Tb((size_t)2 * nw * ov * 8);
+      RISP_HIP(hipMemcpyAsync(Tb.get(), Rb.get(), (size_t)2 * nw * ov * 8, hipMemcpyDeviceToDevice, s));
+      const int nr = orth(Tb, 2 * nw, false);
+      RISP_CHECK(nr > 0, RISP_E_STATE, "full TDDFT: restart basis vanished");
+      store(Tb, 0, nr);
+      nsub = nr;
+      products(0, nsub);
+      update(Pm, WP, nsub, 0, nsub);
+      update(Mm, WM, nsub, 0, nsub);
+      ++res.restarts;
+    }
+    project(T, nsub, nt);
+    const int nk = orth(T, nt, true);
+    if (nk == 0) {  // no new direction: the subspace cannot grow
+      res.t_subspace += tsub.sec();
+      break;
+    }
+    store(T, nsub, nk);
+    res.t_subspace += tsub.sec();
+    products(nsub, nk);
+    update(Pm, WP, nsub + nk, nsub, nk);
+    update(Mm, WM, nsub + nk, nsub, nk);
+    nsub += nk;
+  }
+  RISP_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace risp

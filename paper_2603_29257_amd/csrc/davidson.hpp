@@ -99,4 +99,20 @@ class DavidsonRun {
 
 void davidson(risp_factors* f, const DavOptions& o, const SigmaFn& sigma_fn, DavResult& res);
 
+// Full TDDFT-risp (eq. tddft with eq. hessian): the lowest nstates excitation energies and X + Y,
+// X - Y by a Davidson-like solver on one subspace V for both (A + B) and (A - B) (section on
+// Davidson settings): with Pm = V^T (A + B) V and Mm = V^T (A - B) V (FP64) and Mm = L L^T, the
+// symmetric problem L^T Pm L c = Omega^2 c gives X + Y = V L c / sqrt(Omega) and
+// X - Y = V L^-T c sqrt(Omega); residuals (A + B)(X + Y) - Omega (X - Y) and
+// (A - B)(X - Y) - Omega (X + Y); both preconditioned by 1/(Omega - diag A) and added to V.
+struct FullResult {
+  std::vector<double> omega;  // [nstates]
+  DevBuf XpY, XmY;            // [nstates][ov] FP64
+  int iters = 0, restarts = 0, sigma_vectors = 0;
+  bool converged = false;
+  double t_sigma = 0.0, t_subspace = 0.0, sigma_flops = 0.0;
+  std::vector<double> resid_hist;  // max residual over the states per iteration
+};
+void davidson_full(risp_factors* f, const DavOptions& o, FullResult& res);
+
 }  // namespace risp

@@ -230,6 +230,27 @@ static void transformed_3c(risp_ctx* ctx, hipStream_t s, const DevShells& ao, co
 }
 
 // B = L^-1 T~ over the auxiliary index: T~ [n][cols] -> B [n][cols] (FP64), in ov-column chunks.
+// Txt[a][P][j] = Bx[P][j][a] (FP64 source, FP64 or FP32 destination, row stride ldj)
+template <typename TD>
+__global__ void k_permute_x(const double* __restrict__ Bx, int nP, int no, int nv, TD* __restrict__ out, int ldj) {
+  const int64_t total = (int64_t)nP * no * nv;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(t % nv);
+    const int j = (int)((t / nv) % no);
+    const int P = (int)(t / ((int64_t)nv * no));
+    out[((int64_t)a * nP + P) * ldj + j] = (TD)Bx[t];
+  }
+}
+
+static void permute_x_to_xt(const double* Bx, int nP, int no, int nv, void* out, DType td, int ldj, hipStream_t s) {
+  const int64_t total = (int64_t)nP * no * nv;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
+  if (td == DType::F64) k_permute_x<double><<<grid, 256, 0, s>>>(Bx, nP, no, nv, static_cast<double*>(out), ldj);
+  else k_permute_x<float><<<grid, 256, 0, s>>>(Bx, nP, no, nv, static_cast<float*>(out), ldj);
+  RISP_LAUNCHED();
+}
+
 static void metric_apply(const double* Linv, int n, const double* T, int64_t cols, double* B, hipStream_t s) {
   const int64_t chunk = 1ll << 24;
   for (int64_t c0 = 0; c0 < cols; c0 += chunk) {
@@ -271,6 +292,9 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   RISP_CHECK(prm->j_mode == RISP_J_MO || prm->j_mode == RISP_J_AO_DIRECT, RISP_E_ARG, "bad j_mode");
   RISP_CHECK(prm->j_mode == RISP_J_MO || sys->nao <= kAoMaxNao, RISP_E_SHAPE,
              "the AO Coulomb route takes nao <= " + std::to_string(kAoMaxNao));
+  RISP_CHECK(!prm->full_tddft || (prm->precision != RISP_BF16 && prm->rsh_mode == RISP_RSH_COMBINED &&
+                                   prm->j_mode == RISP_J_MO),
+             RISP_E_ARG, "full TDDFT-risp factors: FP64 or FP32 storage, combined exchange, stored Coulomb route");
   hipStream_t s = stream ? stream : ctx->stream;
   const int nao = sys->nao, nmo = sys->nmo, nocc = sys->nocc, nvir = nmo - nocc;
   f->ctx = ctx;
@@ -282,6 +306,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   f->precision = prm->precision;
   f->has_f32 = prm->precision == RISP_BF16;
   f->j_mode = prm->j_mode;
+  f->full = prm->full_tddft != 0;
 
   // auxiliary bases (section on exchange-space truncation: H omitted, J = s + p, K = s)
   std::vector<risp_shell> auxJ, auxK;
@@ -455,6 +480,21 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
                        Tij.as<double>());
         metric_apply(Linv.as<double>(), nks, Tij.as<double>(), (int64_t)nok * nok,
                      Bij.as<double>() + blk * (size_t)nks * nok * nok, s);
+        RISP_HIP(hipStreamSynchronize(s));
+      }
+      if (f->full) {
+        // full TDDFT-risp: the exchange factor over the window's (i, a) pairs, FP64 [P][i][b], stored
+        // as Tx [P][i][b] (b padded) and Txt [a][P][j] (j padded)
+        DevBuf Tx((size_t)nks * nok * nvk * 8), Bx((size_t)nks * nok * nvk * 8);
+        transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CvKT.as<double>(), nvk,
+                       Tx.as<double>());
+        metric_apply(Linv.as<double>(), nks, Tx.as<double>(), (int64_t)nok * nvk, Bx.as<double>(), s);
+        f->t_x.alloc((size_t)std::max<int64_t>((int64_t)nks * nok * f->nvkp, 1) * dsz);
+        store_rows_padded(Bx.get(), DType::F64, nvk, (int64_t)nks * nok, nvk, f->t_x.get(), tdst, f->nvkp, nullptr, 1,
+                          1, s);
+        f->t_xt.alloc((size_t)std::max<int64_t>((int64_t)nvk * nks * f->nokp, 1) * dsz);
+        fill_zero(f->t_xt.get(), f->t_xt.bytes(), s);
+        permute_x_to_xt(Bx.as<double>(), nks, nok, nvk, f->t_xt.get(), tdst, f->nokp, s);
         RISP_HIP(hipStreamSynchronize(s));
       }
       DevBuf Tab((size_t)nks * na * nvk * 8);
@@ -786,7 +826,9 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
   }
 }
 
-static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s, const SigmaWs& w) {
+// coulomb_only: stop after the Coulomb term (sig = 2 J X, no diagonal, no exchange)
+static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s, const SigmaWs& w,
+                      bool coulomb_only = false) {
   const bool bf = f->precision == RISP_BF16 && !use_f32;
   const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
   const DType tv = f->precision == RISP_FP64 ? DType::F64 : DType::F32;  // X / sigma type
@@ -902,6 +944,7 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
       gemm(g, nullptr, s);
     }
   }
+  if (coulomb_only) return;
   // exchange inside the window
   const int nK = f->naux_k, nok = f->nok, nvk = f->nvk;
   const bool exch = nK > 0 && nok > 0 && nvk > 0;
@@ -1020,6 +1063,99 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   w.k = {f->ws_k.get(), f->ws_k.bytes()};
   w.split = {f->ws_split.get(), f->ws_split.bytes()};
   sigma_run(f, m, X, sig, use_f32, s, w);
+}
+
+// P = A V + 2 J V - KB V and M = A V - 2 J V + KB V, where on entry P holds A V and M holds 2 J V
+template <typename T>
+__global__ void k_combine_full(T* __restrict__ P, T* __restrict__ M, const T* __restrict__ KB, int m, int nocc,
+                               int nvir, const int* __restrict__ po, const int* __restrict__ pv, int nok, int nvk) {
+  const int64_t ov = (int64_t)nocc * nvir, total = (int64_t)m * ov;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ia = t % ov;
+    const int mm = (int)(t / ov);
+    const int i = (int)(ia / nvir), a = (int)(ia % nvir);
+    T kb = (T)0;
+    if (KB) {
+      const int ik = po[i], ak = pv[a];
+      if (ik >= 0 && ak >= 0) kb = KB[((int64_t)mm * nok + ik) * nvk + ak];
+    }
+    const T av = P[t], j2 = M[t];
+    P[t] = av + j2 - kb;
+    M[t] = av - j2 + kb;
+  }
+}
+
+void sigma_full(risp_factors* f, int m, const void* V, void* P, void* M, hipStream_t s) {
+  RISP_CHECK(f->full, RISP_E_STATE, "factors were built without the full-TDDFT exchange factor");
+  RISP_CHECK(f->precision == RISP_FP64 || f->precision == RISP_FP32, RISP_E_ARG, "full TDDFT: FP64 or FP32 factors");
+  if (m <= 0) return;
+  const DType tc = f->precision == RISP_FP64 ? DType::F64 : DType::F32;
+  const size_t csz = dtype_size(tc);
+  // P = A V (leaves the window block of V in ws_xw), M = 2 J V
+  sigma(f, m, V, P, false, s);
+  {
+    SigmaWs w;
+    w.y = {f->ws_y.get(), f->ws_y.bytes()};
+    w.ybf = {f->ws_ybf.get(), f->ws_ybf.bytes()};
+    w.xbf = {f->ws_xbf.get(), f->ws_xbf.bytes()};
+    w.split = {f->ws_split.get(), f->ws_split.bytes()};
+    sigma_run(f, m, V, M, false, s, w, true);
+  }
+  const int nK = f->naux_k, nok = f->nok, nvk = f->nvk, nokp = f->nokp, nvkp = f->nvkp;
+  const bool exch = nK > 0 && nok > 0 && nvk > 0;
+  if (exch) {
+    // KB[m][i][a] = sum_(P, j) H[m][i][P][j] Txt[a][P][j] with H[m][i][P][j] = sum_b Tx[P][i][b] Vw[m][j][b]
+    const int64_t per_h = (int64_t)m * nok * nokp;  // elements of H per auxiliary function
+    const int pc = (int)mt_chunk(nK, per_h, (int64_t)csz);
+    DevBuf H((size_t)per_h * pc * csz);
+    need(f->ws_xw, (size_t)m * nokp * nvkp * csz, "Xw");
+    need(f->ws_k, (size_t)m * nok * nvk * csz, "KB");
+    for (int P0 = 0; P0 < nK; P0 += pc) {
+      const int np = std::min(pc, nK - P0);
+      Gemm g1;  // rows i, columns (m, j), one product per auxiliary function
+      g1.M = nok;
+      g1.N = m * nokp;
+      g1.K = nvkp;
+      g1.tin = g1.tout = tc;
+      g1.A = static_cast<const char*>(f->t_x.get()) + (size_t)P0 * nok * nvkp * csz;
+      g1.lda = nvkp;
+      g1.sa2 = (int64_t)nok * nvkp;
+      g1.B = f->ws_xw.get();
+      g1.ldb = nvkp;
+      g1.C = H.get();
+      g1.ldc = (int64_t)np * nokp;
+      g1.nb2 = np;
+      g1.sc2 = nokp;
+      g1.n_inner = nokp;
+      g1.sc_outer = (int64_t)nok * np * nokp;
+      gemm(g1, nullptr, s);
+      Gemm g2;  // rows (m, i), columns a, contraction over (p, j) of the chunk
+      g2.M = m * nok;
+      g2.N = nvk;
+      g2.K = np * nokp;
+      g2.tin = g2.tout = tc;
+      g2.A = H.get();
+      g2.lda = (int64_t)np * nokp;
+      g2.B = static_cast<const char*>(f->t_xt.get()) + (size_t)P0 * nokp * csz;
+      g2.ldb = (int64_t)nK * nokp;
+      g2.C = f->ws_k.get();
+      g2.ldc = nvk;
+      g2.beta = P0 > 0 ? 1.0 : 0.0;
+      gemm(g2, nullptr, s);
+    }
+  }
+  const int64_t total = (int64_t)m * f->nocc * f->nvir;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 16);
+  if (tc == DType::F64)
+    k_combine_full<double><<<grid, 256, 0, s>>>(static_cast<double*>(P), static_cast<double*>(M),
+                                                exch ? f->ws_k.as<double>() : nullptr, m, f->nocc, f->nvir,
+                                                f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk);
+  else
+    k_combine_full<float><<<grid, 256, 0, s>>>(static_cast<float*>(P), static_cast<float*>(M),
+                                               exch ? f->ws_k.as<float>() : nullptr, m, f->nocc, f->nvir,
+                                               f->pos_o.as<int>(), f->pos_v.as<int>(), nok, nvk);
+  RISP_LAUNCHED();
+  RISP_HIP(hipStreamSynchronize(s));  // H dies at return
 }
 
 // Lays the sigma workspaces of m vectors (stored-precision products) out in [base, base + cap),

@@ -66,6 +66,10 @@ struct risp_factors {
   // BF16 mode, for the correction pass: FP32 copy of T_ia (Coulomb) and the BF16 rounding
   // remainders of T_ij and T_ab (exchange as three BF16 products, hi*hi + lo*hi + hi*lo)
   risp::DevBuf t_ia32, t_ij_lo, t_ab_lo;
+  // full TDDFT-risp: the windowed exchange factor over (i, a) pairs in the stored precision (FP64 or
+  // FP32), as Tx [naux_k][nocc_k][ld_ab] (b contiguous) and Txt [nvir_k][naux_k][ld_ij] ((P, j) contiguous)
+  bool full = false;
+  risp::DevBuf t_x, t_xt;
   risp::DevBuf scale_ia, scale_ia2, scale_k;  // BF16 power-of-two scales (s_P, s_P^2, s_ij s_ab)
   risp::DevBuf occ_k, vir_k, pos_o, pos_v; // window index sets and inverse maps
   risp::DevBuf de64, de32;                 // e_a - e_i
@@ -108,6 +112,11 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
 // the smallest layout, 0 when it fits). The stored-factor Coulomb route only.
 void sigma_scratch(risp_factors* f, int m, const void* X, void* sig, void* scratch, size_t cap, hipStream_t s);
 size_t sigma_scratch_need(const risp_factors* f, int m, size_t cap);
+
+// Full TDDFT-risp products for m vectors V [m][nocc][nvir] (FP64 or FP32 factors built with
+// full_tddft): P = (A + B) V = de V + 4 J V - KA V - KB V and M = (A - B) V = de V - KA V + KB V, where
+// KA is the exchange term of A and KB V_ia = sum_(P, j, b) Tx_ib Tx_ja V_jb over the window.
+void sigma_full(risp_factors* f, int m, const void* V, void* P, void* M, hipStream_t s);
 
 // size the sigma workspaces for m vectors ahead of a graph capture (their allocation synchronises)
 void sigma_prepare(risp_factors* f, int m, bool use_f32);

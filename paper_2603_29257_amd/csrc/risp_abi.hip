@@ -388,6 +388,65 @@ risp_status risp_sigma_noalloc(risp_ctx* ctx, const risp_factors* fc, int32_t m,
   });
 }
 
+risp_status risp_sigma_full(risp_ctx* ctx, const risp_factors* fc, int32_t m, const void* V_dev, void* P_dev,
+                            void* M_dev, int32_t dtype) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(fc != nullptr, RISP_E_ARG, "factors are NULL");
+    RISP_CHECK(fc->ctx == ctx, RISP_E_STATE, "factors belong to another context");
+    RISP_CHECK(m >= 0, RISP_E_ARG, "m must be non-negative");
+    RISP_CHECK(m == 0 || (V_dev && P_dev && M_dev), RISP_E_ARG, "NULL device buffer");
+    const int want = fc->precision == RISP_FP64 ? RISP_FP64 : RISP_FP32;
+    RISP_CHECK(dtype == want, RISP_E_ARG, want == RISP_FP64 ? "FP64 factors take FP64 vectors"
+                                                              : "FP32 factors take FP32 vectors");
+    sigma_full(const_cast<risp_factors*>(fc), m, V_dev, P_dev, M_dev, fc->stream);
+    return RISP_OK;
+  });
+}
+
+risp_status risp_davidson_full(risp_ctx* ctx, const risp_factors* fc, const risp_dav_opts* opts, double* energies,
+                               float* xpy, float* xmy, risp_dav_info* info) {
+  return guarded([&]() -> risp_status {
+    use_ctx(ctx);
+    RISP_CHECK(fc && opts && energies, RISP_E_ARG, "NULL argument");
+    RISP_CHECK(fc->ctx == ctx, RISP_E_STATE, "factors belong to another context");
+    RISP_CHECK(opts->nx0 == 0, RISP_E_ARG, "initial vectors are not supported by the full-TDDFT solver");
+    risp_factors* f = const_cast<risp_factors*>(fc);
+    const int64_t ov = (int64_t)f->nocc * f->nvir;
+    DavOptions o;
+    o.nstates = opts->nstates;
+    o.block = opts->block;
+    o.max_space = opts->max_space;
+    o.max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
+    o.tol = opts->tol;
+    o.log_tag = (opts->flags & RISP_DAV_VERBOSE) ? "full" : nullptr;
+    FullResult r;
+    davidson_full(f, o, r);
+    const int n = (int)std::min<size_t>(opts->nstates, r.omega.size());
+    for (int k = 0; k < n; ++k) energies[k] = r.omega[k];
+    for (float* dst : {xpy, xmy}) {
+      if (!dst || n == 0) continue;
+      std::vector<double> h((size_t)n * ov);
+      RISP_HIP(hipMemcpy(h.data(), (dst == xpy ? r.XpY : r.XmY).get(), h.size() * 8, hipMemcpyDeviceToHost));
+      for (size_t t = 0; t < h.size(); ++t) dst[t] = (float)h[t];
+    }
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->iters = r.iters;
+      info->restarts = r.restarts;
+      info->sigma_vectors = r.sigma_vectors;
+      info->converged = r.converged ? 1 : 0;
+      info->t_build = f->t_build;
+      info->t_sigma = r.t_sigma;
+      info->t_subspace = r.t_subspace;
+      info->sigma_flops = r.sigma_flops;
+      info->hbm_bytes = f->bytes();
+      for (size_t k = 0; k < std::min<size_t>(256, r.resid_hist.size()); ++k) info->resid_hist[k] = r.resid_hist[k];
+    }
+    return r.converged ? RISP_OK : RISP_E_NOTCONV;
+  });
+}
+
 risp_status risp_properties(risp_ctx* ctx, const risp_system* sys, const double* origin, int32_t nstates,
                             const double* energies, const void* X_dev, double* mu, double* mdip, double* f,
                             double* R) {
