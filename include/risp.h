@@ -107,6 +107,9 @@ typedef struct {
   int32_t full_tddft; /* nonzero: also build the windowed exchange factor over (i, a) pairs that
                          full TDDFT-risp needs (Fig. tensors_shape, T_ia^P'); FP64/FP32 factors,
                          combined exchange reading, stored-factor Coulomb route; 0 = TDA only */
+  int32_t dense_transform; /* nonzero: the first MO transform of the build contracts dense (mu nu|P)
+                              slabs; 0 = per-atom partner lists of the kept shell pairs (the same
+                              sums without the screened-out zeros; results equal up to rounding) */
 } risp_params;
 
 typedef struct {

@@ -53,7 +53,7 @@ class ParamsC(C.Structure):
                 ("theta", C.c_double), ("schwarz_tau", C.c_double), ("rsh_mode", C.c_int32),
                 ("window_mode", C.c_int32), ("precision", C.c_int32), ("h_in_aux", C.c_int32),
                 ("bf16_scale", C.c_int32), ("build_chunk_kib", C.c_int32), ("j_mode", C.c_int32),
-                ("full_tddft", C.c_int32)]
+                ("full_tddft", C.c_int32), ("dense_transform", C.c_int32)]
 
 
 class DavOptsC(C.Structure):
@@ -178,11 +178,13 @@ class Params:
     build_chunk_kib: int = 0
     j_mode: int = 0  # J_MO or J_AO_DIRECT
     full_tddft: bool = False  # also build the exchange factor over (i, a) for full TDDFT-risp
+    dense_transform: bool = False  # first MO transform over dense integral slabs (validation)
 
     def c(self):
         return ParamsC(self.c_x, self.beta, self.omega, self.window_ev, self.theta, self.schwarz_tau,
                        self.rsh_mode, self.window_mode, self.precision, int(self.h_in_aux),
-                       int(self.bf16_scale), int(self.build_chunk_kib), int(self.j_mode), int(self.full_tddft))
+                       int(self.bf16_scale), int(self.build_chunk_kib), int(self.j_mode), int(self.full_tddft),
+                       int(self.dense_transform))
 
 
 def device_usage(reset_peak=False):

@@ -229,6 +229,236 @@ static void transformed_3c(risp_ctx* ctx, hipStream_t s, const DevShells& ao, co
   RISP_HIP(hipStreamSynchronize(s));
 }
 
+// Per-atom partner lists of the kept shell pairs: the first transform G[P][i][mu] =
+// sum_nu C[i][nu] (mu nu|P) only needs, for the functions mu of one atom, the functions nu that
+// form a kept pair with one of that atom's shells (on the 1000-atom molecule 14.5 % of nao^2 instead
+// of every nu), so it runs as one small dense product per atom over its partners.
+struct Partners {
+  int ngroups = 0;
+  int64_t S = 0;   // elements of one auxiliary function in the packed layout: sum_g n_g kp_g
+  std::vector<int> mu0, n, kp;
+  std::vector<int64_t> voff, koff;  // per group: sum over earlier groups of n kp, of kp
+  DevBuf idx;                       // [sum kp] partner functions, -1 = padding
+  DevBuf gkoff, gkp;                // per group (device copies of koff, kp)
+  DevBuf fvoff, fng, fkp, fml;      // per AO function: its group's voff, n, kp, and its index in the group
+  DevBuf cab, cba;                  // per kept pair (device list order), see PackMap
+  PackMap map(int nf_stride) const {
+    PackMap m;
+    m.voff = fvoff.as<int64_t>();
+    m.ng = fng.as<int>();
+    m.kp = fkp.as<int>();
+    m.ml = fml.as<int>();
+    m.cab = cab.as<int>();
+    m.cba = cba.as<int>();
+    m.nf_stride = nf_stride;
+    m.elems = (int64_t)nf_stride * S;
+    return m;
+  }
+};
+
+static void build_partners(const risp_system* sys, const PairList& pairs, Partners& P, hipStream_t s) {
+  const int nsh = sys->nshell;
+  std::vector<int> shoff(nsh + 1, 0);
+  for (int k = 0; k < nsh; ++k) shoff[k + 1] = shoff[k] + (sys->shells[k].l == 0 ? 1 : 3);
+  const int nao = shoff[nsh];
+  // groups: runs of consecutive shells on one atom (their functions are contiguous)
+  std::vector<int> gsh(nsh), first;
+  for (int k = 0; k < nsh; ++k) {
+    if (k == 0 || sys->shells[k].atom != sys->shells[k - 1].atom) first.push_back(k);
+    gsh[k] = (int)first.size() - 1;
+  }
+  const int ng = (int)first.size();
+  first.push_back(nsh);
+  std::vector<int> pa(pairs.n), pb(pairs.n);
+  if (pairs.n > 0) {
+    RISP_HIP(hipMemcpyAsync(pa.data(), pairs.a.get(), pairs.n * sizeof(int), hipMemcpyDeviceToHost, s));
+    RISP_HIP(hipMemcpyAsync(pb.data(), pairs.b.get(), pairs.n * sizeof(int), hipMemcpyDeviceToHost, s));
+  }
+  RISP_HIP(hipStreamSynchronize(s));
+  std::vector<std::vector<int>> part(ng), spos(ng);
+  for (int ip = 0; ip < pairs.n; ++ip) {
+    const int A = pa[ip], B = pb[ip];
+    part[gsh[A]].push_back(B);
+    if (A != B) part[gsh[B]].push_back(A);
+  }
+  P.ngroups = ng;
+  P.mu0.resize(ng);
+  P.n.resize(ng);
+  P.kp.resize(ng);
+  P.voff.resize(ng);
+  P.koff.resize(ng);
+  std::vector<int> hidx;
+  std::vector<int64_t> hfvoff(nao);
+  std::vector<int> hfng(nao), hfkp(nao), hfml(nao);
+  int64_t voff = 0, koff = 0;
+  for (int g = 0; g < ng; ++g) {
+    auto& pl = part[g];
+    std::sort(pl.begin(), pl.end());
+    pl.erase(std::unique(pl.begin(), pl.end()), pl.end());
+    int pos = 0;
+    for (int t : pl) {
+      spos[g].push_back(pos);
+      for (int q = shoff[t]; q < shoff[t + 1]; ++q) hidx.push_back(q);
+      pos += shoff[t + 1] - shoff[t];
+    }
+    const int kp = std::max<int>(8, (int)pad8(pos));
+    for (int q = pos; q < kp; ++q) hidx.push_back(-1);
+    P.mu0[g] = shoff[first[g]];
+    P.n[g] = shoff[first[g + 1]] - shoff[first[g]];
+    P.kp[g] = kp;
+    P.voff[g] = voff;
+    P.koff[g] = koff;
+    for (int mu = P.mu0[g]; mu < P.mu0[g] + P.n[g]; ++mu) {
+      hfvoff[mu] = voff;
+      hfng[mu] = P.n[g];
+      hfkp[mu] = kp;
+      hfml[mu] = mu - P.mu0[g];
+    }
+    voff += (int64_t)P.n[g] * kp;
+    koff += kp;
+  }
+  P.S = voff;
+  auto where = [&](int g, int t) {
+    const auto& pl = part[g];
+    const auto it = std::lower_bound(pl.begin(), pl.end(), t);
+    RISP_CHECK(it != pl.end() && *it == t, RISP_E_STATE, "partner list misses a kept pair");
+    return spos[g][it - pl.begin()];
+  };
+  std::vector<int> hcab(pairs.n), hcba(pairs.n);
+  for (int ip = 0; ip < pairs.n; ++ip) {
+    hcab[ip] = where(gsh[pa[ip]], pb[ip]);
+    hcba[ip] = where(gsh[pb[ip]], pa[ip]);
+  }
+  P.idx = upload(hidx.data(), hidx.size(), s);
+  P.gkoff = upload(P.koff.data(), P.koff.size(), s);
+  P.gkp = upload(P.kp.data(), P.kp.size(), s);
+  P.fvoff = upload(hfvoff.data(), hfvoff.size(), s);
+  P.fng = upload(hfng.data(), hfng.size(), s);
+  P.fkp = upload(hfkp.data(), hfkp.size(), s);
+  P.fml = upload(hfml.data(), hfml.size(), s);
+  P.cab = upload(hcab.data(), hcab.size(), s);
+  P.cba = upload(hcba.data(), hcba.size(), s);
+  RISP_HIP(hipStreamSynchronize(s));  // the host arrays die at return
+}
+
+// Cg[g][i][k] = CLT[i][idx[koff_g + k]] (0 for padding) for the groups g0 + blockIdx.y, stored group after
+// group from group g0 on (nl rows of kp_g values each)
+__global__ void k_gather_partner_cols(const double* __restrict__ CLT, int nao, int nl, const int* __restrict__ idx,
+                                      const int64_t* __restrict__ koff, const int* __restrict__ kp, int g0,
+                                      double* __restrict__ out) {
+  const int g = g0 + blockIdx.y;
+  const int64_t ko = koff[g], base = (ko - koff[g0]) * nl;
+  const int K = kp[g];
+  const int64_t total = (int64_t)nl * K;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t / K), k = (int)(t % K);
+    const int nu = idx[ko + k];
+    out[base + t] = nu >= 0 ? CLT[(int64_t)i * nao + nu] : 0.0;
+  }
+}
+
+// transformed_3c over the partner lists: the integrals of each auxiliary chunk go straight into the
+// packed per-atom layout, and the first product runs as one grouped launch of per-atom products
+// (rows i, columns (f, mu) of the atom, K = its padded partner count) writing G[f][i][mu]; the
+// second product is the dense one of transformed_3c.
+constexpr int kPartnerChunkF = 51;             // functions per chunk: groups of 5 and 9 fill 256-wide tiles
+constexpr int64_t kPartnerG = 16ll << 30;      // bytes of G per chunk
+constexpr int64_t kPartnerPack = 8ll << 30;    // bytes of the packed integrals per chunk
+constexpr int64_t kPartnerCg = 6ll << 30;      // bytes of gathered C columns per batch of atoms
+
+static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShells& ao, const PairList& pairs,
+                                    const Partners& P, const DevShells& aux, const Operator& op, const double* CLT,
+                                    int nl, const double* CRT, int nr, double* out) {
+  const int nao = ao.nfunc;
+  const int64_t per_g = (int64_t)nl * nao * 8;
+  const int max_f = (int)std::max<int64_t>(
+      3, std::min<int64_t>({kPartnerChunkF, kPartnerG / std::max<int64_t>(per_g, 1), kPartnerPack / (P.S * 8)}));
+  std::vector<int> l(aux.n);
+  RISP_HIP(hipMemcpyAsync(l.data(), aux.l.get(), aux.n * sizeof(int), hipMemcpyDeviceToHost, s));
+  RISP_HIP(hipStreamSynchronize(s));
+  // batches of consecutive groups whose gathered C columns fit kPartnerCg
+  std::vector<int> bstart{0};
+  for (int g = 0, acc = 0; g < P.ngroups; ++g) {
+    if (acc > 0 && (int64_t)nl * (acc + P.kp[g]) * 8 > kPartnerCg) {
+      bstart.push_back(g);
+      acc = 0;
+    }
+    acc += P.kp[g];
+  }
+  bstart.push_back(P.ngroups);
+  const int nb = (int)bstart.size() - 1;
+  // descriptors and tile numbering of every batch (fixed over the chunks: the packed layout and G
+  // use max_f functions; the rows of a narrower last chunk are zero)
+  const int tiles_m = (nl + 127) / 128;
+  std::vector<GemmGroup> hd(P.ngroups);
+  std::vector<int> ht;  // per batch: tile0 of its groups, then the total
+  std::vector<int> toff(nb), ttot(nb);
+  int64_t cg_max = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int g0 = bstart[b], g1 = bstart[b + 1];
+    toff[b] = (int)ht.size();
+    int64_t tiles = 0;
+    for (int g = g0; g < g1; ++g) {
+      GemmGroup& d = hd[g];
+      d.a_off = (int64_t)nl * (P.koff[g] - P.koff[g0]);
+      d.b_off = (int64_t)max_f * P.voff[g];
+      d.c_off = P.mu0[g];
+      d.K = P.kp[g];
+      d.ld = P.kp[g];
+      d.N = max_f * P.n[g];
+      d.n_inner = P.n[g];
+      ht.push_back((int)tiles);
+      tiles += (int64_t)tiles_m * ((d.N + 255) / 256);
+    }
+    RISP_CHECK(tiles < (1ll << 31), RISP_E_SHAPE, "partner product grid too large");
+    ht.push_back((int)tiles);
+    ttot[b] = (int)tiles;
+    cg_max = std::max<int64_t>(cg_max, (int64_t)nl * (P.koff[g1 - 1] + P.kp[g1 - 1] - P.koff[g0]));
+  }
+  DevBuf dd = upload(hd.data(), hd.size(), s), dt = upload(ht.data(), ht.size(), s);
+  DevBuf Vp((size_t)max_f * P.S * 8), G((size_t)max_f * std::max(nl, 1) * nao * 8 + 8), Cg((size_t)cg_max * 8 + 8);
+  const PackMap pm = P.map(max_f);
+  auto gather = [&](int b) {
+    const int g0 = bstart[b], g1 = bstart[b + 1];
+    k_gather_partner_cols<<<dim3(64, g1 - g0), 256, 0, s>>>(CLT, nao, nl, P.idx.as<int>(), P.gkoff.as<int64_t>(),
+                                                          P.gkp.as<int>(), g0, Cg.as<double>());
+    RISP_LAUNCHED();
+  };
+  if (nb == 1) gather(0);
+  int f0 = 0;
+  for (int s0 = 0; s0 < aux.n;) {
+    int s1 = s0, nf = 0;
+    while (s1 < aux.n && nf + (l[s1] == 0 ? 1 : 3) <= max_f) nf += l[s1++] == 0 ? 1 : 3;
+    int3c(ao, pairs, aux, s0, s1, op, ctx->boys.as<double>(), Vp.as<double>(), s, &pm);
+    for (int b = 0; b < nb; ++b) {
+      if (nb > 1) gather(b);
+      Gemm g = g64(nl, 0, 0);
+      g.A = Cg.get();
+      g.B = Vp.get();
+      g.C = G.get();
+      g.ldc = nao;
+      g.sc_outer = (int64_t)nl * nao;
+      gemm_f64_grouped(g, dd.as<GemmGroup>() + bstart[b], dt.as<int>() + toff[b], bstart[b + 1] - bstart[b], ttot[b],
+                       s);
+    }
+    // out[P][i][a] = sum_mu G[P][i][mu] CRT[a][mu]
+    Gemm h = g64(nl, nr, nao);
+    h.A = G.get();
+    h.lda = nao;
+    h.sa2 = (int64_t)nl * nao;
+    h.B = CRT;
+    h.ldb = nao;
+    h.C = out + (int64_t)f0 * nl * nr;
+    h.ldc = nr;
+    h.sc2 = (int64_t)nl * nr;
+    h.nb2 = nf;
+    gemm(h, nullptr, s);
+    f0 += nf;
+    s0 = s1;
+  }
+  RISP_HIP(hipStreamSynchronize(s));
+}
+
 // B = L^-1 T~ over the auxiliary index: T~ [n][cols] -> B [n][cols] (FP64), in ov-column chunks.
 // Txt[a][P][j] = Bx[P][j][a] (FP64 source, FP64 or FP32 destination, row stride ldj)
 template <typename TD>
@@ -337,6 +567,15 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   PairList pairs;
   screen_pairs(ao, qaux, prm->schwarz_tau, false, pairs, s);
   f->npair = pairs.n;
+  // first transforms over the per-atom partner lists of the kept pairs, or over dense slabs
+  Partners partners;
+  const bool sparse_t = prm->dense_transform == 0;
+  if (sparse_t) build_partners(sys, pairs, partners, s);
+  auto t3c = [&](const DevShells& aux, const Operator& op, const double* CLT, int nl, const double* CRT, int nr,
+                 double* out) {
+    if (sparse_t) transformed_3c_partners(ctx, s, ao, pairs, partners, aux, op, CLT, nl, CRT, nr, out);
+    else transformed_3c(ctx, s, ao, pairs, aux, op, CLT, nl, CRT, nr, out);
+  };
 
   // transposed MO blocks
   DevBuf CoT((size_t)nocc * nao * 8), CvT((size_t)nvir * nao * 8);
@@ -406,7 +645,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     for (int i0 = 0; i0 < nocc; i0 += (int)ni) {
       const int nic = (int)std::min<int64_t>(ni, nocc - i0);
       const int64_t cols = (int64_t)nic * nvir;
-      transformed_3c(ctx, s, ao, pairs, aj, coul, CoT.as<double>() + (size_t)i0 * nao, nic, CvT.as<double>(), nvir,
+      t3c(aj, coul, CoT.as<double>() + (size_t)i0 * nao, nic, CvT.as<double>(), nvir,
                      Tt.as<double>());
       metric_apply_inplace(Linv.as<double>(), nJ, Tt.as<double>(), cols, tmp, s);
       col_sumsq(Tt.as<double>(), nJ, cols, cols, 2.0, f->diag64.as<double>() + (size_t)i0 * nvir, s);
@@ -476,7 +715,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       metric_inverse_cholesky(ctx, s, ak, blocks[blk], Linv);
       {
         DevBuf Tij((size_t)nks * nok * nok * 8);
-        transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
+        t3c(ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
                        Tij.as<double>());
         metric_apply(Linv.as<double>(), nks, Tij.as<double>(), (int64_t)nok * nok,
                      Bij.as<double>() + blk * (size_t)nks * nok * nok, s);
@@ -486,7 +725,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
         // full TDDFT-risp: the exchange factor over the window's (i, a) pairs, FP64 [P][i][b], stored
         // as Tx [P][i][b] (b padded) and Txt [a][P][j] (j padded)
         DevBuf Tx((size_t)nks * nok * nvk * 8), Bx((size_t)nks * nok * nvk * 8);
-        transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CoKT.as<double>(), nok, CvKT.as<double>(), nvk,
+        t3c(ak, blocks[blk], CoKT.as<double>(), nok, CvKT.as<double>(), nvk,
                        Tx.as<double>());
         metric_apply(Linv.as<double>(), nks, Tx.as<double>(), (int64_t)nok * nvk, Bx.as<double>(), s);
         f->t_x.alloc((size_t)std::max<int64_t>((int64_t)nks * nok * f->nvkp, 1) * dsz);
@@ -501,7 +740,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       for (int a0 = 0; a0 < nvk; a0 += (int)na) {
         const int nac = (int)std::min<int64_t>(na, nvk - a0);
         const int64_t cols = (int64_t)nac * nvk;
-        transformed_3c(ctx, s, ao, pairs, ak, blocks[blk], CvKT.as<double>() + (size_t)a0 * nao, nac,
+        t3c(ak, blocks[blk], CvKT.as<double>() + (size_t)a0 * nao, nac,
                        CvKT.as<double>(), nvk, Tab.as<double>());
         metric_apply_inplace(Linv.as<double>(), nks, Tab.as<double>(), cols, tmp, s);
         // chunk element (p, a, a0 + a) is Bx^P_aa of window virtual a0 + a

@@ -67,6 +67,20 @@ bool gemm_bf16_nt_eligible(const Gemm& g);
 int gemm_bf16_nt_tile(const Gemm& g);  // rows of the output tile it would use (128, 192, 256)
 void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s);
 
+// One product of a grouped FP64 launch: (C + c_off)[r][col(c)] = alpha (A + a_off)[r][:] . (B + b_off)[c][:]
+// (+ beta C) over K values, with both operands at row stride ld (a multiple of 2, offsets even) and
+// N output columns split by n_inner as in Gemm (n_inner <= 0: no split).
+struct GemmGroup {
+  int64_t a_off = 0, b_off = 0, c_off = 0;  // element offsets from the launch's A, B and C
+  int K = 0, ld = 0, N = 0, n_inner = 0;
+};
+// Runs ngroups FP64 products of M rows in one launch (A, B, C, M, ldc, sc_outer, alpha, beta from g;
+// FP64 output, no batches, no split-K). tile0 [ngroups + 1] (device) numbers the 128 x 256 output
+// tiles: product k owns tiles [tile0[k], tile0[k + 1]) with at least ceil(M / 128) * ceil(N_k / 256)
+// of them, row tile fastest; total_tiles = tile0[ngroups].
+void gemm_f64_grouped(const Gemm& g, const GemmGroup* groups, const int* tile0, int ngroups, int total_tiles,
+                      hipStream_t s);
+
 // Choose a split-K factor so that the grid covers the chip for products with few output tiles;
 // returns 1 when tiles alone suffice.
 int gemm_auto_split(const Gemm& g);

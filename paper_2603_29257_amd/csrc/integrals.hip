@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_int3c(ShellView AO, ShellView AX, const
                                                const int* __restrict__ pb, int npair,
                                                const int* __restrict__ auxlist, int naux_cls, int f0,
                                                int nao, Operator op, const double* __restrict__ tab,
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out, PackMap pk, int pair0) {
   const int64_t total = (int64_t)npair * naux_cls;
   const int64_t nao2 = (int64_t)nao * nao;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -492,26 +492,47 @@ __global__ __launch_bounds__(256) void k_int3c(ShellView AO, ShellView AX, const
     const double K = 2.0 * pow(M_PI, 2.5) * ip_ / (q * sqrt(p + q)) * Kab;
     base_terms<LA + LB + LC>(K, rho * PC2, rho, op.alpha, op.beta, op.omega, tab, c.S);
     const double nrm = AO.cn[A] * AO.cn[B] * AX.cn[C];
-    double* o = out + (int64_t)(AX.off[C] - f0) * nao2;
     const int oa = AO.off[A], ob = AO.off[B];
     const bool same = (A == B);
-    static_for<0, ncart(LA)>([&](auto ka) {
-      static_for<0, ncart(LB)>([&](auto kb) {
-        static_for<0, ncart(LC)>([&](auto kc) {
-          const double v = os3c<LA, decltype(ka)::value, LB, decltype(kb)::value, LC,
-                                decltype(kc)::value>(c, AB) * nrm;
-          const int mu = oa + decltype(ka)::value, nu = ob + decltype(kb)::value;
-          double* oc = o + (int64_t)decltype(kc)::value * nao2;
-          oc[(int64_t)mu * nao + nu] = v;
-          if (!same) oc[(int64_t)nu * nao + mu] = v;
+    if (pk.voff) {
+      // packed: row mu of A's group at column cab + kb, mirrored row nu of B's group at cba + ka
+      const int fc = AX.off[C] - f0;
+      const int cab = pk.cab[pair0 + ip], cba = pk.cba[pair0 + ip];
+      const int64_t ga = pk.nf_stride * pk.voff[oa], gb = pk.nf_stride * pk.voff[ob];
+      const int nga = pk.ng[oa], ngb = pk.ng[ob], kpa = pk.kp[oa], kpb = pk.kp[ob];
+      const int mla = pk.ml[oa], mlb = pk.ml[ob];
+      static_for<0, ncart(LA)>([&](auto ka) {
+        static_for<0, ncart(LB)>([&](auto kb) {
+          static_for<0, ncart(LC)>([&](auto kc) {
+            const double v = os3c<LA, decltype(ka)::value, LB, decltype(kb)::value, LC,
+                                  decltype(kc)::value>(c, AB) * nrm;
+            const int f = fc + decltype(kc)::value;
+            out[ga + ((int64_t)f * nga + mla + decltype(ka)::value) * kpa + cab + decltype(kb)::value] = v;
+            if (!same)
+              out[gb + ((int64_t)f * ngb + mlb + decltype(kb)::value) * kpb + cba + decltype(ka)::value] = v;
+          });
         });
       });
-    });
+    } else {
+      double* o = out + (int64_t)(AX.off[C] - f0) * nao2;
+      static_for<0, ncart(LA)>([&](auto ka) {
+        static_for<0, ncart(LB)>([&](auto kb) {
+          static_for<0, ncart(LC)>([&](auto kc) {
+            const double v = os3c<LA, decltype(ka)::value, LB, decltype(kb)::value, LC,
+                                  decltype(kc)::value>(c, AB) * nrm;
+            const int mu = oa + decltype(ka)::value, nu = ob + decltype(kb)::value;
+            double* oc = o + (int64_t)decltype(kc)::value * nao2;
+            oc[(int64_t)mu * nao + nu] = v;
+            if (!same) oc[(int64_t)nu * nao + mu] = v;
+          });
+        });
+      });
+    }
   }
 }
 
 void int3c(const DevShells& ao, const PairList& pairs, const DevShells& aux, int s0, int s1,
-           const Operator& op, const double* boys_tab, double* out, hipStream_t s) {
+           const Operator& op, const double* boys_tab, double* out, hipStream_t s, const PackMap* pack) {
   // auxiliary shells of each angular momentum in [s0, s1) (host copy of l and offsets)
   std::vector<int> l(aux.n), off(aux.n);
   RISP_HIP(hipMemcpyAsync(l.data(), aux.l.get(), aux.n * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -522,7 +543,14 @@ void int3c(const DevShells& ao, const PairList& pairs, const DevShells& aux, int
   const int f0 = s0 < aux.n ? off[s0] : 0;
   const int f1 = s1 < aux.n ? off[s1] : aux.nfunc;
   const int nao = ao.nfunc;
-  RISP_HIP(hipMemsetAsync(out, 0, (size_t)(f1 - f0) * nao * nao * sizeof(double), s));
+  PackMap pk;
+  if (pack) {
+    RISP_CHECK(f1 - f0 <= pack->nf_stride, RISP_E_STATE, "int3c: chunk wider than the packed layout");
+    pk = *pack;
+    RISP_HIP(hipMemsetAsync(out, 0, (size_t)pk.elems * sizeof(double), s));
+  } else {
+    RISP_HIP(hipMemsetAsync(out, 0, (size_t)(f1 - f0) * nao * nao * sizeof(double), s));
+  }
   DevBuf lists[2];
   for (int lc = 0; lc < 2; ++lc) lists[lc] = upload(byl[lc].data(), byl[lc].size(), s);
   const ShellView A = view(ao), X = view(aux);
@@ -539,7 +567,7 @@ void int3c(const DevShells& ao, const PairList& pairs, const DevShells& aux, int
       const int* la = lists[lc].as<int>();
 #define RISP_LAUNCH3C(LA_, LB_, LC_)                                                                 \
   k_int3c<LA_, LB_, LC_><<<grid, 256, 0, s>>>(A, X, pa + b0, pb + b0, np, la, na, f0, nao, op,       \
-                                              boys_tab, out)
+                                              boys_tab, out, pk, b0)
       if (cls == 0 && lc == 0) RISP_LAUNCH3C(0, 0, 0);
       else if (cls == 0 && lc == 1) RISP_LAUNCH3C(0, 0, 1);
       else if (cls == 1 && lc == 0) RISP_LAUNCH3C(1, 0, 0);

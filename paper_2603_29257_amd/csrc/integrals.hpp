@@ -47,10 +47,32 @@ double aux_diag_max(const DevShells& aux, const double* boys_tab, hipStream_t s)
 void int2c(const DevShells& aux, const Operator& op, const double* boys_tab, double* out,
            hipStream_t s);
 
+// Packed output of int3c over per-atom partner lists. AO functions fall into groups (runs of
+// consecutive shells on one atom); group g owns functions [mu0_g, mu0_g + n_g) and a sorted list of
+// partner functions (every function of a shell that forms a kept pair with a shell of the group),
+// padded with zeros to kp_g entries. The chunk is stored group after group, each group as
+// [f][mu - mu0_g][position of nu in its list] for the nf_stride auxiliary functions f of the chunk:
+// element (f, mu, nu) lives at nf_stride * voff[mu] + (f * ng[mu] + ml[mu]) * kp[mu] + pos(nu).
+// pos(nu) for a kept pair (A, B) (the pair list's own order and orientation) is cab[pair] + (nu -
+// first function of B) when mu is a function of A, and cba[pair] + (nu - first function of A) in
+// the mirrored position.
+struct PackMap {
+  const int64_t* voff = nullptr;  // [nao] elements per auxiliary function before the group of mu
+  const int* ng = nullptr;        // [nao] functions of the group of mu
+  const int* kp = nullptr;        // [nao] padded partner count of the group of mu
+  const int* ml = nullptr;        // [nao] mu - mu0 of its group
+  const int* cab = nullptr;       // [npair] list position of B's first function in A's group
+  const int* cba = nullptr;       // [npair] list position of A's first function in B's group
+  int nf_stride = 0;
+  int64_t elems = 0;              // elements of one chunk (nf_stride * sum_g n_g kp_g)
+};
+
 // (mu nu|P) with the given operator for auxiliary shells [s0, s1): out dev
-// [nf][nao][nao] (nf = functions of those shells), zeroed first.
+// [nf][nao][nao] (nf = functions of those shells), zeroed first; or, with pack, the packed layout
+// above (zeroed first; nf must not exceed pack->nf_stride).
 void int3c(const DevShells& ao, const PairList& pairs, const DevShells& aux, int s0, int s1,
-           const Operator& op, const double* boys_tab, double* out, hipStream_t s);
+           const Operator& op, const double* boys_tab, double* out, hipStream_t s,
+           const PackMap* pack = nullptr);
 
 // Window predicate on the device: flags[k] = 1 for kept orbitals; counts via compaction.
 void window_sets(const double* mo_energy_dev, int nmo, int nocc, double window_ev, int mode,
