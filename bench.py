@@ -8,6 +8,9 @@ before the timed steps; `value` is its sigma-build throughput (algorithmic flops
 time) and `ms_per_step` its time. Beside the steps, each path runs once end to end from the inputs
 to 15 converged states (factor build + Davidson, with the FP32 correction pass on the BF16 path):
 `time_to_15_states_s` for BF16 and plain FP32, with the phase breakdown, and one FP32 sigma block.
+The FP32 measurements run first, in a child process; the CPU oracle baseline follows, then the BF16
+measurements in this process: device memory freed by one run is cleared by the driver in the
+background, and an allocation that arrives before that is done waits for it inside the timed build.
 
 Prints one JSON line. Inputs are generated on the host before any timed region; the factor build
 takes the MO coefficients from host memory (their PCIe copy is inside the time-to-15-states).
@@ -17,6 +20,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -40,6 +44,11 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison steps")
     ap.add_argument("--no-bf16", action="store_true", help="time only the plain FP32 path (long workloads)")
     ap.add_argument("--verbose", action="store_true", help="one stderr line per Davidson iteration")
+    ap.add_argument("--olsen", action="store_true", help="Olsen's correction vectors in the Davidson solves")
+    ap.add_argument("--part", choices=["bf16", "fp32"], default=None,
+                    help=argparse.SUPPRESS)  # internal: one precision's measurements in a child process
+    ap.add_argument("--bf16-coulomb-fp32", action="store_true",
+                    help="BF16 path: Coulomb term of every sigma from the FP32 copy of T_ia")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ao", action="store_true", help="also time one AO-density Coulomb route sigma block")
     ap.add_argument("--cpu-sample-aux", type=int, default=0,
@@ -188,9 +197,13 @@ def traffic_file(workload):
 
 
 def _source_digest():
+    """Digest of the exchange kernel's sources (its file and the tile header it includes)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2603_29257_amd", "csrc", "gemm_bf16.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("gemm_bf16.hip", "gemm_tile.hpp"):
+        with open(os.path.join(ROOT, "paper_2603_29257_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def recorded_traffic(workload, m):
@@ -276,26 +289,56 @@ def main():
 
     t_gen = time.perf_counter()
     mol = synth.config_system(args.workload)
-    jobs = serving_jobs(args.serving_jobs) if (args.serving and not args.no_serving) else None
+    jobs = serving_jobs(args.serving_jobs) if (args.serving and not args.no_serving and not args.part) else None
     t_gen = time.perf_counter() - t_gen
     log(f"{args.workload}: nao {mol.nao}, nocc {mol.nocc}, nvir {mol.nvir}; generated in {t_gen:.1f} s")
+    precs = ([] if args.no_bf16 else ["bf16"]) + ([] if args.no_fp32 else ["fp32"])
+    if args.part:
+        precs = [args.part]
+    if not precs:
+        sys.exit("nothing to time: --no-bf16 and --no-fp32 together")
+    mp_ = precs[0]  # the path the value and the roofline describe
+    # Device memory that a finished run freed is cleared by the driver in the background before it
+    # can be handed out again; an allocation that comes first waits for it (seconds at this size,
+    # inside the time-to-15-states). So the other precisions run first, each in a child process, and
+    # this process then does its CPU work (the oracle baseline) before it touches the GPU: each path
+    # starts on cleared memory.
+    child = {}
+    if not args.part and not args.no_t2s:
+        for prec in precs[1:]:
+            cmd = [sys.executable, os.path.abspath(__file__), "--part", prec, "--workload", args.workload,
+                   "--m", str(args.m), "--nstates", str(args.nstates), "--tol", str(args.tol)]
+            cmd += [f for f, on in (("--olsen", args.olsen), ("--bf16-coulomb-fp32", args.bf16_coulomb_fp32),
+                                    ("--verbose", args.verbose)) if on]
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True)
+            if r.returncode != 0:
+                sys.exit(f"{prec} measurements failed in their child process (exit status {r.returncode})")
+            child[prec] = json.loads(r.stdout.strip().splitlines()[-1])
+    cpu_base = None
+    if child and not args.no_cpu_baseline:
+        flops_block = next(iter(child.values()))["flops"]  # the same workload in every precision
+        cpu_base = cpu_baseline(mol, args.cpu_sample_aux, m=args.m, gpu_flops=flops_block)
     ctx = P.Context(0)
     sysc = P.System(mol)
     m = args.m
+
+    def params(prec):
+        return P.Params(precision=P.PRECISIONS[prec], bf16_coulomb_fp32=args.bf16_coulomb_fp32)
 
     def t2s(prec):
         """Inputs on the host -> factors -> Davidson to nstates converged states; the factors stay."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F = ctx.build_factors(sysc, P.Params(precision=P.PRECISIONS[prec]))
+        F = ctx.build_factors(sysc, params(prec))
         e, _, info = ctx.davidson(F, args.nstates, tol=args.tol, want_vectors=False, allow_notconv=True,
-                                  verbose=args.verbose)
+                                  verbose=args.verbose, olsen=args.olsen)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         log(f"{prec} time-to-{args.nstates}-states {dt:.2f} s (build {info.t_build:.2f} s, "
             f"{info.iters}+{info.correction_iters} iterations, converged={info.converged})")
         return F, dict(t2s=dt, energies=[float(x) for x in e], iters=info.iters,
                        correction_iters=info.correction_iters, converged=bool(info.converged),
+                       resid_hist=[float(x) for x in info.resid_hist],
                        breakdown={"build": info.t_build, "sigma": info.t_sigma, "subspace": info.t_subspace,
                                   "correction": info.t_correct},
                        sigma_tflops=info.sigma_flops / info.t_sigma / 1e12 if info.t_sigma > 0 else None,
@@ -320,18 +363,19 @@ def main():
         return times
 
     res, t2s_res = {}, {}
-    precs = ([] if args.no_bf16 else ["bf16"]) + ([] if args.no_fp32 else ["fp32"])
-    if not precs:
-        sys.exit("nothing to time: --no-bf16 and --no-fp32 together")
-    mp_ = precs[0]  # the path the value and the roofline describe
+    for prec, c in child.items():
+        t2s_res[prec] = c["t2s"]
+        res[prec] = dict(times=c["times"], flops=c["flops"], prof=None, desc=None, sigma_rows_err=c["sigma_rows_err"])
     for prec in precs:
+        if prec in child:
+            continue
         if args.no_t2s:
-            F = ctx.build_factors(sysc, P.Params(precision=P.PRECISIONS[prec]))
+            F = ctx.build_factors(sysc, params(prec))
         else:
             F, t2s_res[prec] = t2s(prec)
         d = F.desc
         flops = sigma_block_flops(F.desc, m)
-        if prec == mp_:
+        if prec == mp_ and not args.part:
             for k in range(args.warmup):
                 sigma_blocks(F, 1, 0)
                 log(f"warmup {k}")
@@ -348,6 +392,12 @@ def main():
         res[prec] = dict(times=times, flops=flops, prof=prof, desc=d,
                          sigma_rows_err=sigma_rows_check(ctx, F, P, torch, args.workload, m))
         F.free()
+    if args.part:
+        r = res[args.part]
+        print(json.dumps({"t2s": t2s_res[args.part], "times": r["times"], "flops": r["flops"],
+                          "sigma_rows_err": r["sigma_rows_err"]}))
+        ctx.close()
+        return
 
     b = res[mp_]
     t_step = float(np.mean(b["times"]))
@@ -406,7 +456,7 @@ def main():
     if args.ao:
         out["ao_route"] = ao_route_block(ctx, P, sysc, torch, m=m)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mol, args.cpu_sample_aux, m=m, gpu_flops=b["flops"])
+        out["cpu_baseline"] = cpu_base or cpu_baseline(mol, args.cpu_sample_aux, m=m, gpu_flops=b["flops"])
     ctx.close()
     print(json.dumps(out))
 

@@ -101,8 +101,9 @@ typedef struct {
   int32_t bf16_scale; /* BF16 only: 1 stores each auxiliary slice scaled by a power of two */
   int32_t build_chunk_kib; /* device memory for one chunk of FP64 transformed integrals during the
                               build, in KiB; the T_ia and T_ab builds run in as many chunks of
-                              occupied / window-virtual orbitals as needed; 0 = a quarter of the
-                              free device memory, between 1 and 64 GiB */
+                              occupied / window-virtual orbitals as needed; 0 = as large as the
+                              free device memory allows (the stored factors are allocated first,
+                              the build's temporaries then come from one allocation) */
   int32_t j_mode;     /* RISP_J_*: how the Coulomb term of sigma is formed */
   int32_t full_tddft; /* nonzero: also build the windowed exchange factor over (i, a) pairs that
                          full TDDFT-risp needs (Fig. tensors_shape, T_ia^P'); FP64/FP32 factors,
@@ -110,6 +111,9 @@ typedef struct {
   int32_t dense_transform; /* nonzero: the first MO transform of the build contracts dense (mu nu|P)
                               slabs; 0 = per-atom partner lists of the kept shell pairs (the same
                               sums without the screened-out zeros; results equal up to rounding) */
+  int32_t bf16_coulomb_fp32; /* BF16 only: nonzero forms the Coulomb term of every sigma from the FP32
+                                copy of T_ia that the correction pass uses (the exchange stays BF16);
+                                0 = BF16 T_ia */
 } risp_params;
 
 typedef struct {
@@ -136,8 +140,10 @@ typedef struct {
  * size, largest residual over the requested states) to stderr. RISP_DAV_SPILL keeps the subspace
  * vectors and their products (2 (max_space + block) nocc nvir elements) in pinned host memory that
  * the kernels read and write over the host link, for subspaces that do not fit next to the factors
- * (same arithmetic, same results; slower subspace steps). */
-enum { RISP_DAV_VERBOSE = 1, RISP_DAV_SPILL = 2 };
+ * (same arithmetic, same results; slower subspace steps). RISP_DAV_OLSEN forms each correction as
+ * (D - theta)^-1 (r - eps x) with eps chosen so that it is orthogonal to the Ritz vector x (Olsen's
+ * correction; D the diagonal of A) instead of (D - theta)^-1 r. */
+enum { RISP_DAV_VERBOSE = 1, RISP_DAV_SPILL = 2, RISP_DAV_OLSEN = 4 };
 
 typedef struct {
   int32_t iters, restarts, sigma_vectors, converged; /* main stage (BF16 stage for BF16 factors) */

@@ -53,7 +53,8 @@ class ParamsC(C.Structure):
                 ("theta", C.c_double), ("schwarz_tau", C.c_double), ("rsh_mode", C.c_int32),
                 ("window_mode", C.c_int32), ("precision", C.c_int32), ("h_in_aux", C.c_int32),
                 ("bf16_scale", C.c_int32), ("build_chunk_kib", C.c_int32), ("j_mode", C.c_int32),
-                ("full_tddft", C.c_int32), ("dense_transform", C.c_int32)]
+                ("full_tddft", C.c_int32), ("dense_transform", C.c_int32),
+                ("bf16_coulomb_fp32", C.c_int32)]
 
 
 class DavOptsC(C.Structure):
@@ -77,6 +78,7 @@ class PhaseStatC(C.Structure):
 
 DAV_VERBOSE = 1  # risp_dav_opts.flags: one stderr line per Davidson iteration
 DAV_SPILL = 2  # risp_dav_opts.flags: subspace vectors and products in pinned host memory
+DAV_OLSEN = 4  # risp_dav_opts.flags: Olsen's correction vectors
 
 PHASES = ("coulomb_y", "coulomb_j", "exchange_m", "exchange_k", "other")
 
@@ -179,12 +181,13 @@ class Params:
     j_mode: int = 0  # J_MO or J_AO_DIRECT
     full_tddft: bool = False  # also build the exchange factor over (i, a) for full TDDFT-risp
     dense_transform: bool = False  # first MO transform over dense integral slabs (validation)
+    bf16_coulomb_fp32: bool = False  # BF16: Coulomb term from the FP32 copy of T_ia
 
     def c(self):
         return ParamsC(self.c_x, self.beta, self.omega, self.window_ev, self.theta, self.schwarz_tau,
                        self.rsh_mode, self.window_mode, self.precision, int(self.h_in_aux),
                        int(self.bf16_scale), int(self.build_chunk_kib), int(self.j_mode), int(self.full_tddft),
-                       int(self.dense_transform))
+                       int(self.dense_transform), int(self.bf16_coulomb_fp32))
 
 
 def device_usage(reset_peak=False):
@@ -552,7 +555,7 @@ class Context:
 
     def davidson(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, correction_pass=True,
                  x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0, verbose=False,
-                 ncorr=0, correction_ncorr=0, spill=False):
+                 ncorr=0, correction_ncorr=0, spill=False, olsen=False):
         ov = F.nocc * F.nvir
         e = np.zeros(nstates)
         vec = np.zeros((nstates, ov), np.float32) if want_vectors else None
@@ -560,7 +563,8 @@ class Context:
         if x0 is not None:
             x0a = np.ascontiguousarray(x0, dtype=np.float32).reshape(-1, ov)
         o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
-                     0 if x0a is None else x0a.shape[0], (DAV_VERBOSE if verbose else 0) | (DAV_SPILL if spill else 0),
+                     0 if x0a is None else x0a.shape[0],
+                     (DAV_VERBOSE if verbose else 0) | (DAV_SPILL if spill else 0) | (DAV_OLSEN if olsen else 0),
                      None if x0a is None else _ptr(x0a, C.c_float), ncorr, correction_ncorr)
         info = DavInfoC()
         import torch

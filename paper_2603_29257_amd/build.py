@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librisp.so")
-SOURCES = ["integrals.hip", "gemm.hip", "gemm_bf16.hip", "coulomb.hip", "linalg.hip", "factors.hip", "subspace.hip", "davidson.hip",
+SOURCES = ["integrals.hip", "gemm.hip", "gemm_bf16.hip", "gemm_f64.hip", "coulomb.hip", "linalg.hip", "factors.hip", "subspace.hip", "davidson.hip",
            "serve.hip", "properties.hip", "risp_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -64,21 +64,71 @@ __global__ void k_residual(double* __restrict__ AX, const double* __restrict__ X
     AX[t] -= theta[t / ov] * X[t];
 }
 
-// T[r][ia] = R[src[r]][ia] / (theta[src[r]] - de[ia]) with de the diagonal of A, |denominator|
-// floored at 1e-8 (sign kept)
+__device__ __forceinline__ double precond_den(double theta, double de) {
+  double d = theta - de;
+  if (fabs(d) < 1e-8) d = d < 0.0 ? -1e-8 : 1e-8;
+  return d;
+}
+
+// T[r][ia] = (R[k][ia] - eps[r] X[k][ia]) / (theta[k] - de[ia]) for k = src[r], with de the diagonal
+// of A, |denominator| floored at 1e-8 (sign kept); eps = nullptr: plain Davidson correction
 __global__ void k_precond(const double* __restrict__ R, const double* __restrict__ theta,
                           const double* __restrict__ de, const int* __restrict__ src, int nt, int64_t ov,
-                          double* __restrict__ T) {
+                          const double* __restrict__ X, const double* __restrict__ eps, double* __restrict__ T) {
   const int64_t total = (int64_t)nt * ov;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
     const int r = (int)(t / ov);
     const int64_t ia = t % ov;
     const int k = src[r];
-    double d = theta[k] - de[ia];
-    if (fabs(d) < 1e-8) d = d < 0.0 ? -1e-8 : 1e-8;
-    T[t] = R[(int64_t)k * ov + ia] / d;
+    double v = R[(int64_t)k * ov + ia];
+    if (eps) v -= eps[r] * X[(int64_t)k * ov + ia];
+    T[t] = v / precond_den(theta[k], de[ia]);
   }
+}
+
+// Olsen's correction: the two sums x.(D - theta)^-1 r and x.(D - theta)^-1 x per corrected pair, in a
+// fixed order (partial[2][nt][nblk], then eps = first / second)
+__global__ __launch_bounds__(256) void k_olsen_partial(const double* __restrict__ R, const double* __restrict__ X,
+                                                       const double* __restrict__ theta,
+                                                       const double* __restrict__ de, const int* __restrict__ src,
+                                                       int nt, int64_t ov, double* __restrict__ partial) {
+  __shared__ double red[2][256];
+  const int r = blockIdx.y, k = src[r];
+  const int64_t per = (ov + gridDim.x - 1) / gridDim.x;
+  const int64_t b = blockIdx.x * per, e = min(ov, b + per);
+  const double th = theta[k];
+  double sa = 0.0, sb = 0.0;
+  for (int64_t t = b + threadIdx.x; t < e; t += blockDim.x) {
+    const double x = X[(int64_t)k * ov + t], inv = 1.0 / precond_den(th, de[t]);
+    sa += x * R[(int64_t)k * ov + t] * inv;
+    sb += x * x * inv;
+  }
+  red[0][threadIdx.x] = sa;
+  red[1][threadIdx.x] = sb;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + d];
+      red[1][threadIdx.x] += red[1][threadIdx.x + d];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[((int64_t)0 * nt + r) * gridDim.x + blockIdx.x] = red[0][0];
+    partial[((int64_t)1 * nt + r) * gridDim.x + blockIdx.x] = red[1][0];
+  }
+}
+
+__global__ void k_olsen_eps(const double* partial, int nblk, int nt, double* eps) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nt) return;
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < nblk; ++q) {
+    a += partial[(int64_t)r * nblk + q];
+    b += partial[((int64_t)nt + r) * nblk + q];
+  }
+  eps[r] = fabs(b) > 1e-300 ? a / b : 0.0;
 }
 
 __global__ void k_scale_rows(double* T, int nt, int64_t ov, const double* norms) {
@@ -229,6 +279,7 @@ DavidsonRun::DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s) : 
   nblk_ = (int)std::min<int64_t>(64, std::max<int64_t>(1, ov / 4096));
   partial_.alloc((size_t)cap_ * nblk_ * 8);
   norms_.alloc((size_t)cap_ * 8);
+  eps_.alloc((size_t)block_ * 8);
   kept_.alloc(sizeof(int));
   src_.alloc((size_t)block_ * sizeof(int));
   Hn_.alloc((size_t)cap_ * block_ * 8);
@@ -497,8 +548,16 @@ void DavidsonRun::iterate(Timer& tsub) {
   const int nt = (int)todo.size();
   RISP_HIP(hipMemcpyAsync(src_.get(), todo.data(), nt * sizeof(int), hipMemcpyHostToDevice, s_));
   const double* dg = f_->diag64.get() ? f_->diag64.as<double>() : f_->de64.as<double>();
+  if (o_.olsen && nt > 0) {
+    k_olsen_partial<<<dim3(nblk_, nt), 256, 0, s_>>>(AX_.as<double>(), X, theta_.as<double>(), dg, src_.as<int>(),
+                                                     nt, ov, partial_.as<double>());
+    RISP_LAUNCHED();
+    k_olsen_eps<<<ceil_div(nt, 64), 64, 0, s_>>>(partial_.as<double>(), nblk_, nt, eps_.as<double>());
+    RISP_LAUNCHED();
+  }
   k_precond<<<grid_for((int64_t)nt * ov), 256, 0, s_>>>(AX_.as<double>(), theta_.as<double>(), dg,
-                                                        src_.as<int>(), nt, ov, T_.as<double>());
+                                                        src_.as<int>(), nt, ov, X,
+                                                        o_.olsen ? eps_.as<double>() : nullptr, T_.as<double>());
   RISP_LAUNCHED();
   row_norms(T_.as<double>(), nt, norms_.as<double>());
   k_scale_rows<<<grid_for((int64_t)nt * ov), 256, 0, s_>>>(T_.as<double>(), nt, ov, norms_.as<double>());
@@ -892,10 +951,10 @@ void davidson_full(risp_factors* f, const DavOptions& o, FullResult& res) {
     const int nq = (int)todo.size();
     RISP_HIP(hipMemcpyAsync(src.get(), todo.data(), nq * sizeof(int), hipMemcpyHostToDevice, s));
     k_precond<<<grid_for((int64_t)nq * ov), 256, 0, s>>>(R1.as<double>(), om.as<double>(), dg, src.as<int>(), nq, ov,
-                                                         T.as<double>());
+                                                         nullptr, nullptr, T.as<double>());
     RISP_LAUNCHED();
     k_precond<<<grid_for((int64_t)nq * ov), 256, 0, s>>>(R2.as<double>(), om.as<double>(), dg, src.as<int>(), nq, ov,
-                                                         T.as<double>() + (size_t)nq * ov);
+                                                         nullptr, nullptr, T.as<double>() + (size_t)nq * ov);
     RISP_LAUNCHED();
     int nt = 2 * nq;
     {

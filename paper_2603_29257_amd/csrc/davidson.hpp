@@ -34,6 +34,9 @@ struct DavOptions {
   const char* log_tag = nullptr;  // print one line per iteration to stderr under this tag
   int max_corr = 0;  // corrections only for the lowest max_corr Ritz pairs (0: all `block`)
   bool spill = false;  // subspace vectors V and products W in pinned host memory
+  // Olsen's correction t = (D - theta)^-1 (r - eps x) with eps such that t is orthogonal to x (D the
+  // diagonal of A); false: t = (D - theta)^-1 r
+  bool olsen = false;
 };
 
 struct DavResult {
@@ -93,7 +96,7 @@ class DavidsonRun {
   Request rq_;
   DavResult res_;
   std::vector<double> hnorm_, htheta_;
-  DevBuf V_, W_, H_, Hw_, Zs_, eigws_, theta_, AX_, T_, T2_, Cmix_, G_, Cf_, partial_, norms_, kept_,
+  DevBuf V_, W_, H_, Hw_, Zs_, eigws_, theta_, AX_, T_, T2_, Cmix_, G_, Cf_, partial_, norms_, eps_, kept_,
       src_, Hn_, split_, Rv_, Rw_;
 };
 

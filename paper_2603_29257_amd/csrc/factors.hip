@@ -97,6 +97,43 @@ void select_aux(const risp_system* sys, const risp_params* prm, std::vector<risp
   }
 }
 
+// Non-owning view of device memory: a sigma workspace (a DevBuf of the factor object, or a piece of
+// a fixed scratch buffer) or a piece of the build's arena.
+struct WsView {
+  void* p = nullptr;
+  size_t n = 0;
+  void* get() const { return p; }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+  size_t bytes() const { return n; }
+};
+
+// One device allocation that the build's large temporaries are carved from (bump allocation,
+// released back to a mark). Device memory that was used and then freed is cleared by the driver
+// before it is handed out again (measured at tens of GB/s), so freeing and reallocating large
+// temporaries between the build's phases costs seconds on the large molecules; the arena is
+// allocated once.
+class Arena {
+ public:
+  static size_t round(size_t b) { return (b + 255) / 256 * 256; }
+  void reserve(size_t bytes) {
+    buf_.alloc(std::max<size_t>(bytes, 256));
+    off_ = 0;
+  }
+  WsView take(size_t bytes) {
+    const size_t b = round(std::max<size_t>(bytes, 1));
+    RISP_CHECK(off_ + b <= buf_.bytes(), RISP_E_STATE, "build arena exhausted");
+    WsView v{static_cast<char*>(buf_.get()) + off_, b};
+    off_ += b;
+    return v;
+  }
+  size_t mark() const { return off_; }
+  void release_to(size_t m) { off_ = m; }
+
+ private:
+  DevBuf buf_;
+  size_t off_ = 0;
+};
+
 static Gemm g64(int M, int N, int K) {
   Gemm g;
   g.M = M;
@@ -106,26 +143,20 @@ static Gemm g64(int M, int N, int K) {
   return g;
 }
 
-// Stored factor: `rows` rows of `cols` values padded to `ldd` (a multiple of 8, zero padding), in the
-// storage precision; BF16 rows are divided by the power-of-two scale of their auxiliary slice
-// (scale index (row / div) % mod). Next to BF16 factors the BF16 rounding remainder (same layout and
-// scales) is kept when asked for.
-struct Stored {
-  DevBuf main, lo;
-};
-// default bytes of one FP64 chunk of transformed integrals: a quarter of the free device memory at
-// the start of the build, between 1 and 64 GiB (fewer chunks = fewer passes over the integrals)
-constexpr int64_t kBuildChunkMin = 1ll << 30, kBuildChunkMax = 64ll << 30;
 constexpr int64_t kIntChunk = 16ll << 30;    // bytes of one chunk of dense (mu nu|P) slices in the build
 
 // T <- Linv T in place for T [n][cols] (row stride cols), through column panels of at most ~1 GiB
-static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t cols, DevBuf& tmp, hipStream_t s) {
+// (tmp holds one panel: metric_panel_bytes)
+static int64_t metric_panel_cols(int n, int64_t cols) {
+  return std::max<int64_t>(8, std::min<int64_t>(cols, ((1ll << 30) / (8 * (int64_t)std::max(n, 1))) / 8 * 8));
+}
+static size_t metric_panel_bytes(int n, int64_t cols) {
+  return Arena::round((size_t)std::max(n, 1) * metric_panel_cols(n, cols) * 8);
+}
+static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t cols, const WsView& tmp, hipStream_t s) {
   if (n == 0 || cols == 0) return;
-  const int64_t w = std::max<int64_t>(8, std::min<int64_t>(cols, ((1ll << 30) / (8 * (int64_t)n)) / 8 * 8));
-  if (tmp.bytes() < (size_t)n * w * 8) {
-    RISP_HIP(hipStreamSynchronize(s));  // earlier panels may still read the old buffer
-    tmp.alloc((size_t)n * w * 8);
-  }
+  const int64_t w = metric_panel_cols(n, cols);
+  RISP_CHECK(tmp.bytes() >= (size_t)n * w * 8, RISP_E_STATE, "metric panel buffer too small");
   for (int64_t c0 = 0; c0 < cols; c0 += w) {
     const int nc = (int)std::min<int64_t>(w, cols - c0);
     Gemm g = g64(n, nc, n);
@@ -141,23 +172,18 @@ static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t c
   }
 }
 
-static void store_factor(const double* B, int64_t rows, int64_t cols, int64_t ldd, int precision, bool keep_lo,
-                         const float* scale, int64_t div, int64_t mod, Stored& out, hipStream_t s) {
+// rows of FP64 B [rows][cols] into the preallocated stored factor (row stride ldd, zero padding; BF16
+// rows divided by the power-of-two scale (row / div) % mod, remainder into lo when given)
+static void store_factor(const double* B, int64_t rows, int64_t cols, int64_t ldd, int precision,
+                         const float* scale, int64_t div, int64_t mod, DevBuf& main, DevBuf* lo, hipStream_t s) {
   const int64_t n = std::max<int64_t>(rows * ldd, 1);
-  if (precision == RISP_FP64) {
-    out.main.alloc(n * 8);
-    store_rows_padded(B, DType::F64, cols, rows, cols, out.main.get(), DType::F64, ldd, nullptr, 1, 1, s);
-  } else if (precision == RISP_FP32) {
-    out.main.alloc(n * 4);
-    store_rows_padded(B, DType::F64, cols, rows, cols, out.main.get(), DType::F32, ldd, nullptr, 1, 1, s);
-  } else {
-    out.main.alloc(n * 2);
-    store_rows_padded(B, DType::F64, cols, rows, cols, out.main.get(), DType::BF16, ldd, scale, div, mod, s);
-    if (keep_lo) {
-      out.lo.alloc(n * 2);
-      store_rows_padded_lo(B, DType::F64, cols, rows, cols, out.main.get(), out.lo.get(), ldd, scale, div, mod, s);
-    }
-  }
+  const DType td = precision == RISP_FP64 ? DType::F64 : (precision == RISP_FP32 ? DType::F32 : DType::BF16);
+  RISP_CHECK(main.bytes() >= (size_t)n * dtype_size(td) && (!lo || lo->bytes() >= (size_t)n * 2), RISP_E_STATE,
+             "stored factor buffer too small");
+  store_rows_padded(B, DType::F64, cols, rows, cols, main.get(), td, ldd, td == DType::BF16 ? scale : nullptr,
+                    div, mod, s);
+  if (td == DType::BF16 && lo)
+    store_rows_padded_lo(B, DType::F64, cols, rows, cols, main.get(), lo->get(), ldd, scale, div, mod, s);
 }
 
 // power-of-two scales of `slices` contiguous FP64 slices of `len` values (ones when disabled)
@@ -366,26 +392,46 @@ constexpr int64_t kPartnerG = 16ll << 30;      // bytes of G per chunk
 constexpr int64_t kPartnerPack = 8ll << 30;    // bytes of the packed integrals per chunk
 constexpr int64_t kPartnerCg = 6ll << 30;      // bytes of gathered C columns per batch of atoms
 
-static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShells& ao, const PairList& pairs,
-                                    const Partners& P, const DevShells& aux, const Operator& op, const double* CLT,
-                                    int nl, const double* CRT, int nr, double* out) {
-  const int nao = ao.nfunc;
-  const int64_t per_g = (int64_t)nl * nao * 8;
-  const int max_f = (int)std::max<int64_t>(
-      3, std::min<int64_t>({kPartnerChunkF, kPartnerG / std::max<int64_t>(per_g, 1), kPartnerPack / (P.S * 8)}));
-  std::vector<int> l(aux.n);
-  RISP_HIP(hipMemcpyAsync(l.data(), aux.l.get(), aux.n * sizeof(int), hipMemcpyDeviceToHost, s));
-  RISP_HIP(hipStreamSynchronize(s));
-  // batches of consecutive groups whose gathered C columns fit kPartnerCg
-  std::vector<int> bstart{0};
-  for (int g = 0, acc = 0; g < P.ngroups; ++g) {
+// Buffers of one transformed_3c_partners call for nl left orbitals: functions per auxiliary chunk,
+// batches of consecutive groups (gathered C columns within kPartnerCg, unless one group alone is
+// larger) and the bytes taken from the arena.
+struct PartnerPlan {
+  int max_f = 0;
+  std::vector<int> bstart;
+  int64_t cg_elems = 0;
+  size_t bytes = 0;
+};
+static PartnerPlan partner_plan(const Partners& P, int nl, int nao) {
+  PartnerPlan pl;
+  const int64_t per_g = (int64_t)std::max(nl, 1) * nao * 8;
+  pl.max_f = (int)std::max<int64_t>(
+      3, std::min<int64_t>({kPartnerChunkF, kPartnerG / per_g, kPartnerPack / std::max<int64_t>(P.S * 8, 1)}));
+  pl.bstart.push_back(0);
+  int64_t acc = 0;
+  for (int g = 0; g < P.ngroups; ++g) {
     if (acc > 0 && (int64_t)nl * (acc + P.kp[g]) * 8 > kPartnerCg) {
-      bstart.push_back(g);
+      pl.bstart.push_back(g);
       acc = 0;
     }
     acc += P.kp[g];
+    pl.cg_elems = std::max<int64_t>(pl.cg_elems, (int64_t)nl * acc);
   }
-  bstart.push_back(P.ngroups);
+  pl.bstart.push_back(P.ngroups);
+  pl.bytes = Arena::round((size_t)pl.max_f * P.S * 8) + Arena::round((size_t)pl.max_f * std::max(nl, 1) * nao * 8) +
+             Arena::round((size_t)pl.cg_elems * 8 + 8);
+  return pl;
+}
+
+static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShells& ao, const PairList& pairs,
+                                    const Partners& P, const DevShells& aux, const Operator& op, const double* CLT,
+                                    int nl, const double* CRT, int nr, double* out, Arena& ar) {
+  const int nao = ao.nfunc;
+  const PartnerPlan pl = partner_plan(P, nl, nao);
+  const int max_f = pl.max_f;
+  const std::vector<int>& bstart = pl.bstart;
+  std::vector<int> l(aux.n);
+  RISP_HIP(hipMemcpyAsync(l.data(), aux.l.get(), aux.n * sizeof(int), hipMemcpyDeviceToHost, s));
+  RISP_HIP(hipStreamSynchronize(s));
   const int nb = (int)bstart.size() - 1;
   // descriptors and tile numbering of every batch (fixed over the chunks: the packed layout and G
   // use max_f functions; the rows of a narrower last chunk are zero)
@@ -393,7 +439,6 @@ static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShell
   std::vector<GemmGroup> hd(P.ngroups);
   std::vector<int> ht;  // per batch: tile0 of its groups, then the total
   std::vector<int> toff(nb), ttot(nb);
-  int64_t cg_max = 0;
   for (int b = 0; b < nb; ++b) {
     const int g0 = bstart[b], g1 = bstart[b + 1];
     toff[b] = (int)ht.size();
@@ -413,10 +458,11 @@ static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShell
     RISP_CHECK(tiles < (1ll << 31), RISP_E_SHAPE, "partner product grid too large");
     ht.push_back((int)tiles);
     ttot[b] = (int)tiles;
-    cg_max = std::max<int64_t>(cg_max, (int64_t)nl * (P.koff[g1 - 1] + P.kp[g1 - 1] - P.koff[g0]));
   }
   DevBuf dd = upload(hd.data(), hd.size(), s), dt = upload(ht.data(), ht.size(), s);
-  DevBuf Vp((size_t)max_f * P.S * 8), G((size_t)max_f * std::max(nl, 1) * nao * 8 + 8), Cg((size_t)cg_max * 8 + 8);
+  const size_t m0 = ar.mark();
+  const WsView Vp = ar.take((size_t)max_f * P.S * 8), G = ar.take((size_t)max_f * std::max(nl, 1) * nao * 8),
+               Cg = ar.take((size_t)pl.cg_elems * 8 + 8);
   const PackMap pm = P.map(max_f);
   auto gather = [&](int b) {
     const int g0 = bstart[b], g1 = bstart[b + 1];
@@ -457,6 +503,7 @@ static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShell
     s0 = s1;
   }
   RISP_HIP(hipStreamSynchronize(s));
+  ar.release_to(m0);
 }
 
 // B = L^-1 T~ over the auxiliary index: T~ [n][cols] -> B [n][cols] (FP64), in ov-column chunks.
@@ -537,6 +584,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   f->has_f32 = prm->precision == RISP_BF16;
   f->j_mode = prm->j_mode;
   f->full = prm->full_tddft != 0;
+  f->coul32 = prm->precision == RISP_BF16 && prm->bf16_coulomb_fp32 != 0;
 
   // auxiliary bases (section on exchange-space truncation: H omitted, J = s + p, K = s)
   std::vector<risp_shell> auxJ, auxK;
@@ -571,41 +619,140 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   Partners partners;
   const bool sparse_t = prm->dense_transform == 0;
   if (sparse_t) build_partners(sys, pairs, partners, s);
+  Arena ar;
   auto t3c = [&](const DevShells& aux, const Operator& op, const double* CLT, int nl, const double* CRT, int nr,
                  double* out) {
-    if (sparse_t) transformed_3c_partners(ctx, s, ao, pairs, partners, aux, op, CLT, nl, CRT, nr, out);
+    if (sparse_t) transformed_3c_partners(ctx, s, ao, pairs, partners, aux, op, CLT, nl, CRT, nr, out, ar);
     else transformed_3c(ctx, s, ao, pairs, aux, op, CLT, nl, CRT, nr, out);
   };
+  // arena bytes of one t3c call with nl left orbitals (the dense path allocates its own buffers)
+  auto t3c_bytes = [&](int nl) -> size_t { return sparse_t ? partner_plan(partners, nl, nao).bytes : 0; };
 
   // transposed MO blocks
   DevBuf CoT((size_t)nocc * nao * 8), CvT((size_t)nvir * nao * 8);
   gather_transpose(C.as<double>(), nmo, nao, nullptr, 0, nocc, CoT.as<double>(), s);
   gather_transpose(C.as<double>(), nmo, nao, nullptr, nocc, nvir, CvT.as<double>(), s);
 
-  // ---- Coulomb factor T_ia ----
-  // Built in chunks of occupied orbitals so the FP64 intermediate stays within chunk_bytes
-  // (one chunk up to a few hundred atoms): transformed integrals (Q|ia), the metric applied in place,
-  // then stored rows. BF16 factors go through their FP32 copy: the per-slice scales need the maximum
-  // over every chunk, and the BF16 rows are written from the FP32 copy at the end.
+  // exchange operator blocks (combined reading: one; split reading: 1/r and erf(omega r)/r)
+  std::vector<Operator> blocks;
+  if (prm->c_x != 0.0 || prm->beta != 0.0) {
+    if (prm->rsh_mode == RISP_RSH_COMBINED) {
+      blocks.push_back({prm->c_x, prm->beta, prm->omega});
+    } else {
+      if (prm->c_x != 0.0) blocks.push_back({prm->c_x, 0.0, 0.0});
+      if (prm->beta != 0.0) blocks.push_back({0.0, prm->beta, prm->omega});
+    }
+  }
+  const int nks = ak.nfunc;
+  const int nok = f->nok, nvk = f->nvk;
+  f->naux_k = (int)blocks.size() * nks;
+  const bool exch = f->naux_k > 0 && nok > 0 && nvk > 0;
+  if (!exch) f->naux_k = 0;
+  const int nK = f->naux_k;
+  const bool jmo = f->j_mode != RISP_J_AO_DIRECT;
+  const int nJ = aj.nfunc;
+  const int64_t ov = (int64_t)nocc * nvir;
+  f->ld_ia = pad8(ov);
+  f->nokp = (int)pad8(nok);
+  f->nvkp = (int)pad8(nvk);
+
+  // ---- stored factors, allocated before any temporary ----
+  // BF16 factors also keep the FP32 copy of T_ia and the BF16 remainders of T_ij and T_ab (the
+  // correction pass); T_ia goes through its FP32 copy (the per-slice scales need the maximum over
+  // every chunk) and T_ab through an FP32 staging block in the arena.
   const bool bf = prm->precision == RISP_BF16;
   const DType tdst = prm->precision == RISP_FP64 ? DType::F64 : DType::F32;
-  f->diag64.alloc((size_t)std::max<int64_t>((int64_t)nocc * nvir, 1) * 8);
-  fill_zero(f->diag64.get(), f->diag64.bytes(), s);
-  RISP_CHECK(prm->build_chunk_kib >= 0, RISP_E_ARG, "build_chunk_kib must be non-negative");
-  int64_t chunk_bytes = (int64_t)prm->build_chunk_kib << 10;
-  if (chunk_bytes == 0) {
-    size_t fr = 0, tot = 0;
-    RISP_HIP(hipMemGetInfo(&fr, &tot));
-    chunk_bytes = std::max(kBuildChunkMin, std::min(kBuildChunkMax, (int64_t)(fr / 4)));
-  }
   const size_t dsz = dtype_size(tdst);
-  if (f->j_mode == RISP_J_AO_DIRECT) {
+  const size_t esz = bf ? 2 : dsz;  // stored element
+  f->diag64.alloc((size_t)std::max<int64_t>(ov, 1) * 8);
+  fill_zero(f->diag64.get(), f->diag64.bytes(), s);
+  if (jmo) {
+    DevBuf& dst = bf ? f->t_ia32 : f->t_ia;
+    dst.alloc((size_t)std::max<int64_t>((int64_t)nJ * f->ld_ia, 1) * dsz);
+    fill_zero(dst.get(), dst.bytes(), s);  // zero padding columns
+    if (bf) f->t_ia.alloc((size_t)std::max<int64_t>((int64_t)nJ * f->ld_ia, 1) * 2);
+  }
+  const size_t n_ab = (size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1);
+  const size_t n_ij = (size_t)std::max<int64_t>((int64_t)nok * nK * f->nokp, 1);
+  if (exch) {
+    // written chunk by chunk, padding stays zero; BF16 factors stage the FP32 values as their two
+    // 16-bit halves in t_ab and t_ab_lo and convert them in place once the slice scales are known
+    f->t_ab.alloc(n_ab * esz);
+    fill_zero(f->t_ab.get(), f->t_ab.bytes(), s);
+    if (bf) {
+      f->t_ab_lo.alloc(n_ab * 2);
+      fill_zero(f->t_ab_lo.get(), f->t_ab_lo.bytes(), s);
+    }
+    f->t_ij.alloc(n_ij * esz);
+    if (bf) f->t_ij_lo.alloc(n_ij * 2);
+    if (f->full) {
+      f->t_x.alloc((size_t)std::max<int64_t>((int64_t)nks * nok * f->nvkp, 1) * dsz);
+      f->t_xt.alloc((size_t)std::max<int64_t>((int64_t)nvk * nks * f->nokp, 1) * dsz);
+      fill_zero(f->t_xt.get(), f->t_xt.bytes(), s);
+    }
+  }
+
+  // ---- the arena: chunk sizes planned against the free device memory ----
+  RISP_CHECK(prm->build_chunk_kib >= 0, RISP_E_ARG, "build_chunk_kib must be non-negative");
+  size_t fr = 0, tot = 0;
+  RISP_HIP(hipMemGetInfo(&fr, &tot));
+  // room left for the small allocations of the build, for the dense-slab path's own buffers, and for
+  // a following Davidson solve (default block of 30 and subspace of 270 vectors with their products,
+  // Ritz and correction rows, sigma workspaces): its allocations then find device memory that no
+  // earlier allocation used, which the driver does not have to clear first
+  const int64_t vsz = prm->precision == RISP_FP64 ? 8 : 4, blk = 30, cap = 9 * blk;
+  const int64_t dav = 2 * cap * ov * vsz + 4 * blk * ov * 8 + 4 * blk * ov * vsz + blk * f->ld_ia * 4 +
+                      (exch ? std::min<int64_t>(4ll << 30, (int64_t)nK * blk * nvk * f->nokp * 4) +
+                                  blk * (int64_t)f->nokp * f->nvkp * 4 + 5 * blk * (int64_t)nok * nvk * 4
+                            : 0);
+  const int64_t keep = (2ll << 30) + (int64_t)(0.02 * (double)tot) + (sparse_t ? 0 : (20ll << 30));
+  const int64_t budget = std::max<int64_t>(1ll << 30, (int64_t)fr - keep - dav);
+  // FP64 chunk of transformed integrals: build_chunk_kib when given
+  const int64_t chunk_cap = prm->build_chunk_kib > 0 ? ((int64_t)prm->build_chunk_kib << 10) : budget;
+  // rows per chunk: all when they fit, else the largest multiple of 128 (the transforms' row tile)
+  auto plan_rows = [&](int n, int64_t per_row, auto&& bytes_for) -> int {
+    auto fits = [&](int r) { return r * per_row <= chunk_cap && (int64_t)bytes_for(r) <= budget; };
+    if (fits(n)) return std::max(n, 1);
+    int r = std::max(1, (int)std::min<int64_t>(n, chunk_cap / std::max<int64_t>(per_row, 1)));
+    if (r >= 128) r = r / 128 * 128;
+    while (r > 128 && !fits(r)) r -= 128;
+    while (r > 1 && !fits(r)) r = r > 128 ? r - 128 : r / 2;
+    return r;
+  };
+  int ni = 0, na = 0;
+  size_t need_j = 0, need_k = 0, k_persist = 0;
+  if (jmo) {
+    const int64_t per_row = (int64_t)nJ * std::max(nvir, 1) * 8;
+    auto bytes_j = [&](int r) {
+      return Arena::round((size_t)per_row * r) + metric_panel_bytes(nJ, (int64_t)r * nvir) + t3c_bytes(r);
+    };
+    ni = plan_rows(nocc, per_row, bytes_j);
+    need_j = bytes_j(ni);
+  }
+  if (exch) {
+    k_persist = Arena::round((size_t)nK * nok * nok * 8) + Arena::round((size_t)nK * nvk * 8);
+    const size_t step_ij = Arena::round((size_t)nks * nok * nok * 8) + t3c_bytes(nok);
+    const size_t step_x = f->full ? 2 * Arena::round((size_t)nks * nok * nvk * 8) + t3c_bytes(nok) : 0;
+    const size_t after = Arena::round((size_t)nK * nok * nok * 8);  // T_ij in [i][P][j] order (FP64)
+    const int64_t per_row = (int64_t)nks * nvk * 8;
+    auto bytes_k = [&](int r) {
+      const size_t tab = Arena::round((size_t)per_row * r) + metric_panel_bytes(nks, (int64_t)r * nvk) + t3c_bytes(r);
+      return k_persist + std::max({step_ij, step_x, tab, after});
+    };
+    na = plan_rows(nvk, per_row, bytes_k);
+    need_k = bytes_k(na);
+  }
+  ar.reserve(std::max(need_j, need_k));
+
+  // ---- Coulomb factor T_ia ----
+  // Built in chunks of ni occupied orbitals: transformed integrals (Q|ia), the metric applied in
+  // place, then stored rows.
+  if (!jmo) {
     // no stored T_ia: keep the metric factor and plan the auxiliary chunks of the per-sigma integral
     // passes (dense (mu nu|P) slices of at most ~2 GiB, whole shells)
     Operator coul;
     metric_inverse_cholesky(ctx, s, aj, coul, f->linv_j);
     f->j_op = coul;
-    f->ld_ia = pad8((int64_t)nocc * nvir);
     const int64_t per_func = (int64_t)nao * nao * 8;
     const int max_f = (int)std::max<int64_t>(3, std::min<int64_t>(256, (2ll << 30) / per_func));
     const int ns = (int)auxJ.size();
@@ -631,35 +778,24 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     Operator coul;  // 1/r
     DevBuf Linv;
     metric_inverse_cholesky(ctx, s, aj, coul, Linv);
-    const int nJ = aj.nfunc;
-    const int64_t ov = (int64_t)nocc * nvir;
-    f->ld_ia = pad8(ov);
     DevBuf& dst = bf ? f->t_ia32 : f->t_ia;
-    dst.alloc((size_t)std::max<int64_t>((int64_t)nJ * f->ld_ia, 1) * dsz);
-    fill_zero(dst.get(), dst.bytes(), s);  // zero padding columns
-    DevBuf mx((size_t)std::max(nJ, 1) * 8), tmp;
-    // occupied orbitals per chunk: a multiple of 128 (the transforms' row tile) when more than one chunk
-    int64_t ni = std::max<int64_t>(1, std::min<int64_t>(nocc, chunk_bytes / ((int64_t)nJ * std::max(nvir, 1) * 8)));
-    if (ni < nocc && ni >= 128) ni = ni / 128 * 128;
-    DevBuf Tt((size_t)nJ * ni * std::max(nvir, 1) * 8);
-    for (int i0 = 0; i0 < nocc; i0 += (int)ni) {
-      const int nic = (int)std::min<int64_t>(ni, nocc - i0);
+    DevBuf mx((size_t)std::max(nJ, 1) * 8);
+    const size_t m0 = ar.mark();
+    const WsView Tt = ar.take((size_t)nJ * ni * std::max(nvir, 1) * 8);
+    const WsView tmp = ar.take(metric_panel_bytes(nJ, (int64_t)ni * nvir));
+    for (int i0 = 0; i0 < nocc; i0 += ni) {
+      const int nic = std::min(ni, nocc - i0);
       const int64_t cols = (int64_t)nic * nvir;
-      t3c(aj, coul, CoT.as<double>() + (size_t)i0 * nao, nic, CvT.as<double>(), nvir,
-                     Tt.as<double>());
+      t3c(aj, coul, CoT.as<double>() + (size_t)i0 * nao, nic, CvT.as<double>(), nvir, Tt.as<double>());
       metric_apply_inplace(Linv.as<double>(), nJ, Tt.as<double>(), cols, tmp, s);
       col_sumsq(Tt.as<double>(), nJ, cols, cols, 2.0, f->diag64.as<double>() + (size_t)i0 * nvir, s);
       if (bf) row_absmax(Tt.as<double>(), nJ, cols, cols, mx.as<double>(), i0 > 0, s);
       store_block(Tt.get(), DType::F64, cols, 0, static_cast<char*>(dst.get()) + (size_t)i0 * nvir * dsz, tdst,
                   f->ld_ia, 0, 1, nJ, cols, s);
     }
-    RISP_HIP(hipStreamSynchronize(s));
-    Tt.release();
-    tmp.release();
     if (bf) {
       f->scale_ia.alloc((size_t)std::max(nJ, 1) * sizeof(float));
       pow2_from_max(mx.as<double>(), nJ, prm->bf16_scale != 0, f->scale_ia.as<float>(), s);
-      f->t_ia.alloc((size_t)std::max<int64_t>((int64_t)nJ * f->ld_ia, 1) * 2);
       store_rows_padded(f->t_ia32.get(), DType::F32, f->ld_ia, nJ, f->ld_ia, f->t_ia.get(), DType::BF16, f->ld_ia,
                         f->scale_ia.as<float>(), 1, std::max(nJ, 1), s);
       f->scale_ia2.alloc((size_t)std::max(nJ, 1) * sizeof(float));
@@ -668,22 +804,11 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       RISP_LAUNCHED();
     }
     RISP_HIP(hipStreamSynchronize(s));  // mx and Linv die at the end of this scope
+    ar.release_to(m0);
   }
 
   // ---- exchange factors T_ij, T_ab in the J^ metric ----
-  std::vector<Operator> blocks;
-  if (prm->c_x != 0.0 || prm->beta != 0.0) {
-    if (prm->rsh_mode == RISP_RSH_COMBINED) {
-      blocks.push_back({prm->c_x, prm->beta, prm->omega});
-    } else {
-      if (prm->c_x != 0.0) blocks.push_back({prm->c_x, 0.0, 0.0});
-      if (prm->beta != 0.0) blocks.push_back({0.0, prm->beta, prm->omega});
-    }
-  }
-  const int nks = ak.nfunc;
-  f->naux_k = (int)blocks.size() * nks;
-  const int nok = f->nok, nvk = f->nvk;
-  if (f->naux_k > 0 && nok > 0 && nvk > 0) {
+  if (exch) {
     DevBuf CoKT((size_t)nok * nao * 8), CvKT((size_t)nvk * nao * 8);
     gather_transpose(C.as<double>(), nmo, nao, f->occ_k.as<int>(), 0, nok, CoKT.as<double>(), s);
     // virtual window columns are nocc + vir_k[b]: gather through a shifted index list
@@ -696,65 +821,62 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       gather_transpose(C.as<double>(), nmo, nao, dv.as<int>(), 0, nvk, CvKT.as<double>(), s);
       RISP_HIP(hipStreamSynchronize(s));
     }
-    const int nK = f->naux_k;
-    // T_ij stored [i][P][j] (j padded) for the second exchange product; T_ab [P][a][b] (b padded)
-    f->nokp = (int)pad8(nok);
-    f->nvkp = (int)pad8(nvk);
-    // T_ab goes straight to its stored rows in chunks of window virtuals a (as T_ia above)
-    DevBuf ab32;  // BF16 mode: FP32 staging of T_ab until the slice scales are known
-    DevBuf& dab = bf ? ab32 : f->t_ab;
-    dab.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * dsz);
-    fill_zero(dab.get(), dab.bytes(), s);
-    DevBuf mxab((size_t)std::max(nK, 1) * 8), tmp;
-    DevBuf Baa((size_t)nK * nvk * 8);  // Bx^P_aa, for the diagonal of A
-    int64_t na = std::max<int64_t>(1, std::min<int64_t>(nvk, chunk_bytes / ((int64_t)nks * nvk * 8)));
-    if (na < nvk && na >= 128) na = na / 128 * 128;
-    DevBuf Bij((size_t)nK * nok * nok * 8);
+    // T_ij stored [i][P][j] (j padded) for the second exchange product; T_ab [P][a][b] (b padded),
+    // written chunk by chunk of window virtuals a (BF16 factors: into an FP32 staging block until
+    // the slice scales are known)
+    const size_t m0 = ar.mark();
+    const WsView Bij = ar.take((size_t)nK * nok * nok * 8);
+    const WsView Baa = ar.take((size_t)nK * nvk * 8);  // Bx^P_aa, for the diagonal of A
+    DevBuf mxab((size_t)std::max(nK, 1) * 8);
     for (size_t blk = 0; blk < blocks.size(); ++blk) {
       DevBuf Linv;
       metric_inverse_cholesky(ctx, s, ak, blocks[blk], Linv);
       {
-        DevBuf Tij((size_t)nks * nok * nok * 8);
-        t3c(ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok,
-                       Tij.as<double>());
+        const size_t mk = ar.mark();
+        const WsView Tij = ar.take((size_t)nks * nok * nok * 8);
+        t3c(ak, blocks[blk], CoKT.as<double>(), nok, CoKT.as<double>(), nok, Tij.as<double>());
         metric_apply(Linv.as<double>(), nks, Tij.as<double>(), (int64_t)nok * nok,
                      Bij.as<double>() + blk * (size_t)nks * nok * nok, s);
         RISP_HIP(hipStreamSynchronize(s));
+        ar.release_to(mk);
       }
       if (f->full) {
         // full TDDFT-risp: the exchange factor over the window's (i, a) pairs, FP64 [P][i][b], stored
         // as Tx [P][i][b] (b padded) and Txt [a][P][j] (j padded)
-        DevBuf Tx((size_t)nks * nok * nvk * 8), Bx((size_t)nks * nok * nvk * 8);
-        t3c(ak, blocks[blk], CoKT.as<double>(), nok, CvKT.as<double>(), nvk,
-                       Tx.as<double>());
+        const size_t mk = ar.mark();
+        const WsView Tx = ar.take((size_t)nks * nok * nvk * 8), Bx = ar.take((size_t)nks * nok * nvk * 8);
+        t3c(ak, blocks[blk], CoKT.as<double>(), nok, CvKT.as<double>(), nvk, Tx.as<double>());
         metric_apply(Linv.as<double>(), nks, Tx.as<double>(), (int64_t)nok * nvk, Bx.as<double>(), s);
-        f->t_x.alloc((size_t)std::max<int64_t>((int64_t)nks * nok * f->nvkp, 1) * dsz);
         store_rows_padded(Bx.get(), DType::F64, nvk, (int64_t)nks * nok, nvk, f->t_x.get(), tdst, f->nvkp, nullptr, 1,
                           1, s);
-        f->t_xt.alloc((size_t)std::max<int64_t>((int64_t)nvk * nks * f->nokp, 1) * dsz);
-        fill_zero(f->t_xt.get(), f->t_xt.bytes(), s);
         permute_x_to_xt(Bx.as<double>(), nks, nok, nvk, f->t_xt.get(), tdst, f->nokp, s);
         RISP_HIP(hipStreamSynchronize(s));
+        ar.release_to(mk);
       }
-      DevBuf Tab((size_t)nks * na * nvk * 8);
-      for (int a0 = 0; a0 < nvk; a0 += (int)na) {
-        const int nac = (int)std::min<int64_t>(na, nvk - a0);
+      const size_t mk = ar.mark();
+      const WsView Tab = ar.take((size_t)nks * na * nvk * 8);
+      const WsView tmp = ar.take(metric_panel_bytes(nks, (int64_t)na * nvk));
+      for (int a0 = 0; a0 < nvk; a0 += na) {
+        const int nac = std::min(na, nvk - a0);
         const int64_t cols = (int64_t)nac * nvk;
-        t3c(ak, blocks[blk], CvKT.as<double>() + (size_t)a0 * nao, nac,
-                       CvKT.as<double>(), nvk, Tab.as<double>());
+        t3c(ak, blocks[blk], CvKT.as<double>() + (size_t)a0 * nao, nac, CvKT.as<double>(), nvk, Tab.as<double>());
         metric_apply_inplace(Linv.as<double>(), nks, Tab.as<double>(), cols, tmp, s);
         // chunk element (p, a, a0 + a) is Bx^P_aa of window virtual a0 + a
         gather_strided(Tab.as<double>() + a0, nks, nac, (int64_t)nac * nvk, nvk + 1,
                        Baa.as<double>() + (size_t)blk * nks * nvk + a0, nvk, s);
         if (bf) row_absmax(Tab.as<double>(), nks, cols, cols, mxab.as<double>() + blk * nks, a0 > 0, s);
         // rows (p, a) of the chunk -> stored rows (blk * nks + p) * nvk + a0 + a
-        store_block(Tab.get(), DType::F64, nvk, nac,
-                    static_cast<char*>(dab.get()) + ((size_t)blk * nks * nvk + a0) * f->nvkp * dsz, tdst, f->nvkp, nvk,
-                    nks, nac, nvk, s);
+        const size_t r0 = ((size_t)blk * nks * nvk + a0) * f->nvkp;
+        if (bf)
+          store_block_split(Tab.as<double>(), nvk, nac, f->t_ab.as<uint16_t>() + r0, f->t_ab_lo.as<uint16_t>() + r0,
+                            f->nvkp, nvk, nks, nac, nvk, s);
+        else
+          store_block(Tab.get(), DType::F64, nvk, nac, static_cast<char*>(f->t_ab.get()) + r0 * dsz, tdst, f->nvkp,
+                      nvk, nks, nac, nvk, s);
       }
       RISP_HIP(hipStreamSynchronize(s));
+      ar.release_to(mk);
     }
-    tmp.release();
     {
       // exchange part of the diagonal: K_ia = sum_P Bx^P_ii Bx^P_aa inside the window
       DevBuf Bii((size_t)nK * nok * 8), Kd((size_t)nok * nvk * 8);
@@ -778,24 +900,15 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       slice_scales(Bij.as<double>(), nK, (int64_t)nok * nok, prm->bf16_scale != 0, sij, s);
       sab.alloc((size_t)std::max(nK, 1) * sizeof(float));
       pow2_from_max(mxab.as<double>(), nK, prm->bf16_scale != 0, sab.as<float>(), s);
-      f->t_ab.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * 2);
-      store_rows_padded(ab32.get(), DType::F32, f->nvkp, (int64_t)nK * nvk, f->nvkp, f->t_ab.get(), DType::BF16,
-                        f->nvkp, sab.as<float>(), nvk, nK, s);
-      f->t_ab_lo.alloc((size_t)std::max<int64_t>((int64_t)nK * nvk * f->nvkp, 1) * 2);
-      store_rows_padded_lo(ab32.get(), DType::F32, f->nvkp, (int64_t)nK * nvk, f->nvkp, f->t_ab.get(),
-                           f->t_ab_lo.get(), f->nvkp, sab.as<float>(), nvk, nK, s);
+      split_to_bf16_pair(f->t_ab.get(), f->t_ab_lo.get(), (int64_t)nK * nvk, f->nvkp, sab.as<float>(), nvk, nK, s);
       RISP_HIP(hipStreamSynchronize(s));
-      ab32.release();  // the correction pass uses hi + lo
     }
     {
-      DevBuf Bp((size_t)nK * nok * nok * 8);  // FP64 [i][P][j]
+      const WsView Bp = ar.take((size_t)nK * nok * nok * 8);  // FP64 [i][P][j]
       permute_pij_ipj(Bij.as<double>(), nK, nok, nok, 8, Bp.get(), s);
-      Stored st;
-      store_factor(Bp.as<double>(), (int64_t)nok * nK, nok, f->nokp, prm->precision, f->has_f32, sij.as<float>(), 1,
-                   nK, st, s);
+      store_factor(Bp.as<double>(), (int64_t)nok * nK, nok, f->nokp, prm->precision, sij.as<float>(), 1, nK, f->t_ij,
+                   bf ? &f->t_ij_lo : nullptr, s);
       RISP_HIP(hipStreamSynchronize(s));
-      f->t_ij = std::move(st.main);
-      f->t_ij_lo = std::move(st.lo);
     }
     if (bf) {
       f->scale_k.alloc(nK * sizeof(float));
@@ -803,8 +916,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       RISP_LAUNCHED();
     }
     RISP_HIP(hipStreamSynchronize(s));
-  } else {
-    f->naux_k = 0;
+    ar.release_to(m0);
   }
 
   // orbital gaps
@@ -871,7 +983,7 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   } else {
     f->ws_y.alloc((size_t)f->naux_j * m * acc);
     // Coulomb passes of BF16 and FP32 factors: X with the row stride of T_ia, Yt [64][nJp]
-    const size_t xe = cs >= 4 ? 4 : 2;
+    const size_t xe = (cs >= 4 || f->coul32) ? 4 : 2;
     f->ws_ybf.alloc((size_t)kCoulombMaxM * pad_to(f->naux_j, 32) * xe + 16);
     f->ws_xbf.alloc((size_t)m * f->ld_ia * xe + 16);
     split_bytes = std::max((size_t)kMaxSplit * f->naux_j * m * acc,
@@ -904,15 +1016,6 @@ static void need(const DevBuf& b, size_t bytes, const char* what) {
   RISP_CHECK(b.bytes() >= bytes, RISP_E_STATE, std::string("sigma workspace too small: ") + what);
 }
 
-// Non-owning view of one sigma workspace (a DevBuf of the factor object, or a piece of a fixed
-// scratch buffer).
-struct WsView {
-  void* p = nullptr;
-  size_t n = 0;
-  void* get() const { return p; }
-  template <typename T> T* as() const { return static_cast<T*>(p); }
-  size_t bytes() const { return n; }
-};
 static void need(const WsView& b, size_t bytes, const char* what) {
   RISP_CHECK(b.bytes() >= bytes, RISP_E_STATE, std::string("sigma workspace too small: ") + what);
 }
@@ -1076,15 +1179,17 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
   const int64_t ov = (int64_t)f->nocc * f->nvir;
   const int nJ = f->naux_j;
   const int64_t ldt = f->ld_ia;  // padded row stride of T_ia
-  // correction-pass arithmetic of BF16 factors: FP32 Coulomb, split-BF16 exchange
+  // correction-pass arithmetic of BF16 factors: FP32 Coulomb, split-BF16 exchange; coul32: the BF16
+  // stage forms its Coulomb term from the FP32 copy of T_ia as well
   const bool split = f->precision == RISP_BF16 && use_f32;
-  const void* Tia = split ? f->t_ia32.get() : f->t_ia.get();
+  const bool c32 = split || (bf && f->coul32);
+  const void* Tia = c32 ? f->t_ia32.get() : f->t_ia.get();
   const void* Tij = f->t_ij.get();
   const void* Tab = f->t_ab.get();
   const size_t esz = dtype_size(tc);
   if (f->j_mode == RISP_J_AO_DIRECT) {
     coulomb_ao(f, m, X, tv, sig, pb, s);
-  } else if (bf) {
+  } else if (bf && !c32) {
     need(w.xbf, (size_t)m * ldt * 2, "X (BF16)");
     need(w.ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 2, "Yt (BF16)");
     // BF16 copy of X with the row stride of T_ia (zero padding), then the two skinny passes
@@ -1113,7 +1218,7 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
                        static_cast<float*>(sig) + (size_t)g0 * ov, s);
       }
     }
-  } else if (tc == DType::F32) {
+  } else if (tc == DType::F32 || c32) {
     // FP32 copy of X with the row stride of T_ia (zero padding), then the two skinny FP32 passes
     need(w.xbf, (size_t)m * ldt * 4, "X (padded)");
     need(w.ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * 4, "Yt");
@@ -1416,7 +1521,7 @@ static size_t carve_scratch(const risp_factors* f, int m, SigmaWs& w, char* base
   if (tc == DType::F64) {
     take(w.y, (size_t)nJ * m * acc);
   } else {
-    const size_t xe = tc == DType::BF16 ? 2 : 4;
+    const size_t xe = (tc == DType::BF16 && !f->coul32) ? 2 : 4;
     take(w.ybf, (size_t)kCoulombMaxM * pad_to(nJ, 32) * xe + 16);
     take(w.xbf, (size_t)m * f->ld_ia * xe + 16);
     split_min = coulomb_y_workspace(nJ, std::min(m, kCoulombMaxM), f->ld_ia);

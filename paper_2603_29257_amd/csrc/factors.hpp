@@ -69,6 +69,7 @@ struct risp_factors {
   // full TDDFT-risp: the windowed exchange factor over (i, a) pairs in the stored precision (FP64 or
   // FP32), as Tx [naux_k][nocc_k][ld_ab] (b contiguous) and Txt [nvir_k][naux_k][ld_ij] ((P, j) contiguous)
   bool full = false;
+  bool coul32 = false;  // BF16 mode: the Coulomb term of every sigma from t_ia32
   risp::DevBuf t_x, t_xt;
   risp::DevBuf scale_ia, scale_ia2, scale_k;  // BF16 power-of-two scales (s_P, s_P^2, s_ij s_ab)
   risp::DevBuf occ_k, vir_k, pos_o, pos_v; // window index sets and inverse maps

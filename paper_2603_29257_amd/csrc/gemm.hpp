@@ -66,6 +66,7 @@ void gemm(const Gemm& g, void* work, hipStream_t s);
 bool gemm_bf16_nt_eligible(const Gemm& g);
 int gemm_bf16_nt_tile(const Gemm& g);  // rows of the output tile it would use (128, 192, 256)
 void gemm_bf16_nt(const Gemm& g, void* work, hipStream_t s);
+void gemm_f64_nt(const Gemm& g, void* work, hipStream_t s);  // FP64 operands (gemm_bf16_nt forwards them)
 
 // One product of a grouped FP64 launch: (C + c_off)[r][col(c)] = alpha (A + a_off)[r][:] . (B + b_off)[c][:]
 // (+ beta C) over K values, with both operands at row stride ld (a multiple of 2, offsets even) and

@@ -316,6 +316,57 @@ void store_block(const void* src, DType ts, int64_t lds, int64_t sps, void* dst,
   RISP_LAUNCHED();
 }
 
+// FP64 block -> FP32 values kept as their upper and lower 16-bit halves in two arrays (the two BF16
+// arrays of a split factor used as FP32 staging), same indexing as k_store_block
+__global__ void k_store_block_split(const double* __restrict__ src, int64_t lds, int64_t sps, uint16_t* __restrict__ hi,
+                                    uint16_t* __restrict__ lo, int64_t ldd, int64_t dps, int64_t nr, int64_t nc,
+                                    int64_t total) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t % nc, r = (t / nc) % nr, p = t / (nc * nr);
+    const uint32_t u = __float_as_uint(cvt<double, float>(src[(p * sps + r) * lds + c]));
+    const int64_t d = (p * dps + r) * ldd + c;
+    hi[d] = (uint16_t)(u >> 16);
+    lo[d] = (uint16_t)(u & 0xFFFFu);
+  }
+}
+
+void store_block_split(const double* src, int64_t lds, int64_t sps, void* hi, void* lo, int64_t ldd, int64_t dps,
+                       int64_t np, int64_t nr, int64_t nc, hipStream_t s) {
+  const int64_t total = np * nr * nc;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 18);
+  k_store_block_split<<<grid, 256, 0, s>>>(src, lds, sps, static_cast<uint16_t*>(hi), static_cast<uint16_t*>(lo), ldd,
+                                          dps, nr, nc, total);
+  RISP_LAUNCHED();
+}
+
+// In place: the FP32 value staged as halves (hi, lo) becomes its scaled BF16 rounding in hi and the
+// BF16 rounding of the remainder in lo, exactly as store_rows_padded + store_rows_padded_lo from an
+// FP32 source (zeros stay zeros)
+__global__ void k_split_to_bf16_pair(uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int64_t total, int64_t ldd,
+                                     const float* __restrict__ scale, int64_t div, int64_t mod) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const float x = __uint_as_float(((uint32_t)hi[t] << 16) | (uint32_t)lo[t]);
+    double v = (double)x;
+    if (scale) v /= (double)scale[((t / ldd) / div) % mod];  // exact: powers of two
+    const uint16_t h = cvt<double, uint16_t>(v);
+    hi[t] = h;
+    lo[t] = f2bf_rne((float)(v - (double)bf2f_(h)));
+  }
+}
+
+void split_to_bf16_pair(void* hi, void* lo, int64_t rows, int64_t ldd, const float* scale, int64_t div, int64_t mod,
+                        hipStream_t s) {
+  const int64_t total = rows * ldd;
+  if (total == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 1 << 18);
+  k_split_to_bf16_pair<<<grid, 256, 0, s>>>(static_cast<uint16_t*>(hi), static_cast<uint16_t*>(lo), total, ldd, scale,
+                                           div, mod);
+  RISP_LAUNCHED();
+}
+
 template <typename TS, typename TD>
 __global__ void k_store_padded(const TS* __restrict__ src, int64_t lds, int64_t rows, int64_t cols,
                                TD* __restrict__ dst, int64_t ldd, const float* __restrict__ scale, int64_t div,

@@ -44,6 +44,13 @@ void pow2_from_max(const double* mx, int n, bool enabled, float* scale, hipStrea
 void store_block(const void* src, DType ts, int64_t lds, int64_t sps, void* dst, DType td, int64_t ldd, int64_t dps,
                  int64_t np, int64_t nr, int64_t nc, hipStream_t s);
 
+// store_block of an FP64 source into FP32 values kept as upper / lower 16-bit halves in hi and lo
+void store_block_split(const double* src, int64_t lds, int64_t sps, void* hi, void* lo, int64_t ldd, int64_t dps,
+                       int64_t np, int64_t nr, int64_t nc, hipStream_t s);
+// in place: staged halves -> BF16 rows scaled by scale[(row / div) % mod] in hi, the remainder in lo
+void split_to_bf16_pair(void* hi, void* lo, int64_t rows, int64_t ldd, const float* scale, int64_t div, int64_t mod,
+                        hipStream_t s);
+
 // T [P][i][j] -> out [i][P][j]  (element size esz bytes)
 void permute_pij_ipj(const void* T, int nP, int ni, int nj, size_t esz, void* out, hipStream_t s);
 

@@ -518,6 +518,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
     o.tol = opts->tol;
     o.max_corr = opts->ncorr > 0 ? opts->ncorr : opts->nstates;
     o.spill = (opts->flags & RISP_DAV_SPILL) != 0;
+    o.olsen = (opts->flags & RISP_DAV_OLSEN) != 0;
     DevBuf x0;
     if (opts->nx0 > 0) {
       RISP_CHECK(opts->x0 != nullptr, RISP_E_ARG, "x0 is NULL");

@@ -161,6 +161,7 @@ void Server::admit(Job& j) {
   o.tol = j.opts.tol;
   o.max_corr = j.opts.ncorr > 0 ? j.opts.ncorr : j.opts.nstates;
   o.spill = (j.opts.flags & RISP_DAV_SPILL) != 0;
+  o.olsen = (j.opts.flags & RISP_DAV_OLSEN) != 0;
   if (j.prm.precision == RISP_BF16) {
     if (j.opts.correction_pass) o.tol = std::max(o.tol, j.opts.bf16_tol > 0.0 ? j.opts.bf16_tol : 1e-4);
     o.stall_iters = 2;
@@ -354,6 +355,7 @@ void Server::loop() {
             oc.block = j.opts.block;
             oc.max_corr = j.opts.correction_ncorr > 0 ? j.opts.correction_ncorr : j.opts.nstates;
             oc.spill = (j.opts.flags & RISP_DAV_SPILL) != 0;
+            oc.olsen = (j.opts.flags & RISP_DAV_OLSEN) != 0;
             oc.max_space = j.opts.max_space;
             oc.tol = j.opts.tol;
             oc.x0_dev = j.main_res.X.as<double>();

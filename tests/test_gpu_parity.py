@@ -448,3 +448,39 @@ def test_errors_are_reported(ctx, mol0):
     bad.nocc = bad.mo_coeff.shape[1]
     with pytest.raises(P.RispError):
         _gpu_factors(ctx, bad)
+
+
+@pytest.mark.parametrize("m", [7, 70])
+def test_sigma_bf16_with_fp32_coulomb(ctx, mol0, oracle0, m):
+    # BF16 exchange with the Coulomb term from the FP32 copy of T_ia (bf16_coulomb_fp32): within the
+    # BF16 bar, and its Coulomb part equal to the FP32 path's (the exchange-free variant isolates it)
+    import paper_2603_29257_amd as P
+    F = _gpu_factors(ctx, mol0, precision=P.BF16, bf16_coulomb_fp32=True)
+    X = synth.random_trial_vectors(m, F.nocc, F.nvir, 23)
+    ref = R.sigma(oracle0, X)
+    Xd = torch.tensor(X, dtype=torch.float32, device=ctx.device)
+    got = ctx.sigma(F, Xd).cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _print(f"sigma bf16 + FP32 Coulomb m={m} max rel err {err:.3e}")
+    assert err <= BF16_SIGMA_TOL
+    F.free()
+    Fb = _gpu_factors(ctx, mol0, precision=P.BF16, bf16_coulomb_fp32=True, c_x=0.0, beta=0.0)
+    Ff = _gpu_factors(ctx, mol0, precision=P.FP32, c_x=0.0, beta=0.0)
+    a, b = ctx.sigma(Fb, Xd).cpu().numpy(), ctx.sigma(Ff, Xd).cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(b).max()
+    Fb.free()
+    Ff.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_davidson_olsen_energies_config0(ctx, mol0, oracle0, prec):
+    # Olsen's correction vectors (RISP_DAV_OLSEN) reach the same eigenpairs
+    import paper_2603_29257_amd as P
+    w, _ = R.lowest_eigh(R.dense_A(oracle0), 5)
+    F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
+    e, _, info = ctx.davidson(F, 5, tol=1e-5, olsen=True)
+    _print(f"davidson {prec} with Olsen corrections: iters {info.iters}+{info.correction_iters}, "
+           f"max |dE| {np.abs(e - w).max():.3e}")
+    assert info.converged
+    assert np.abs(e - w).max() <= (1e-6 if prec == "fp32" else 2e-5)
+    F.free()
