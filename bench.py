@@ -314,10 +314,14 @@ def main():
             if r.returncode != 0:
                 sys.exit(f"{prec} measurements failed in their child process (exit status {r.returncode})")
             child[prec] = json.loads(r.stdout.strip().splitlines()[-1])
+    t_child_end = time.perf_counter()
     cpu_base = None
     if child and not args.no_cpu_baseline:
         flops_block = next(iter(child.values()))["flops"]  # the same workload in every precision
         cpu_base = cpu_baseline(mol, args.cpu_sample_aux, m=args.m, gpu_flops=flops_block)
+    if child:
+        # give the driver time to clear the memory the child process used (untimed)
+        time.sleep(max(0.0, 12.0 - (time.perf_counter() - t_child_end)))
     ctx = P.Context(0)
     sysc = P.System(mol)
     m = args.m

@@ -142,8 +142,12 @@ typedef struct {
  * the kernels read and write over the host link, for subspaces that do not fit next to the factors
  * (same arithmetic, same results; slower subspace steps). RISP_DAV_OLSEN forms each correction as
  * (D - theta)^-1 (r - eps x) with eps chosen so that it is orthogonal to the Ritz vector x (Olsen's
- * correction; D the diagonal of A) instead of (D - theta)^-1 r. */
-enum { RISP_DAV_VERBOSE = 1, RISP_DAV_SPILL = 2, RISP_DAV_OLSEN = 4 };
+ * correction; D the diagonal of A) instead of (D - theta)^-1 r. The correction pass of BF16
+ * factors rounds the basis vectors it multiplies to BF16 values, so its split-BF16 exchange skips
+ * the vectors' lo halves, and solves the subspace problem with their overlap;
+ * RISP_DAV_FP32_BASIS keeps FP32 basis vectors there instead (three split products per
+ * contraction). */
+enum { RISP_DAV_VERBOSE = 1, RISP_DAV_SPILL = 2, RISP_DAV_OLSEN = 4, RISP_DAV_FP32_BASIS = 8 };
 
 typedef struct {
   int32_t iters, restarts, sigma_vectors, converged; /* main stage (BF16 stage for BF16 factors) */

@@ -79,6 +79,7 @@ class PhaseStatC(C.Structure):
 DAV_VERBOSE = 1  # risp_dav_opts.flags: one stderr line per Davidson iteration
 DAV_SPILL = 2  # risp_dav_opts.flags: subspace vectors and products in pinned host memory
 DAV_OLSEN = 4  # risp_dav_opts.flags: Olsen's correction vectors
+DAV_FP32_BASIS = 8  # risp_dav_opts.flags: FP32 basis vectors in the BF16 correction pass
 
 PHASES = ("coulomb_y", "coulomb_j", "exchange_m", "exchange_k", "other")
 
@@ -555,7 +556,7 @@ class Context:
 
     def davidson(self, F: Factors, nstates, tol=1e-5, block=0, max_space=0, max_iter=0, correction_pass=True,
                  x0=None, want_vectors=True, allow_notconv=False, correction_steps=0, bf16_tol=0.0, verbose=False,
-                 ncorr=0, correction_ncorr=0, spill=False, olsen=False):
+                 ncorr=0, correction_ncorr=0, spill=False, olsen=False, fp32_basis=False):
         ov = F.nocc * F.nvir
         e = np.zeros(nstates)
         vec = np.zeros((nstates, ov), np.float32) if want_vectors else None
@@ -564,7 +565,8 @@ class Context:
             x0a = np.ascontiguousarray(x0, dtype=np.float32).reshape(-1, ov)
         o = DavOptsC(nstates, block, max_space, max_iter, tol, int(correction_pass), correction_steps, bf16_tol,
                      0 if x0a is None else x0a.shape[0],
-                     (DAV_VERBOSE if verbose else 0) | (DAV_SPILL if spill else 0) | (DAV_OLSEN if olsen else 0),
+                     (DAV_VERBOSE if verbose else 0) | (DAV_SPILL if spill else 0) | (DAV_OLSEN if olsen else 0)
+                     | (DAV_FP32_BASIS if fp32_basis else 0),
                      None if x0a is None else _ptr(x0a, C.c_float), ncorr, correction_ncorr)
         info = DavInfoC()
         import torch

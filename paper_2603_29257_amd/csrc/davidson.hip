@@ -195,6 +195,23 @@ __global__ void k_store_rows(const double* __restrict__ T, int64_t n, TS* __rest
 // Hn [nall][nn] = V[0:nall] . W[n0:n0+nn]^T. Columns n0.. of H (and rows, by symmetry) take Hn; the
 // new-new block takes the average of Hn and its transpose, so H is exactly symmetric and every cell
 // has exactly one writer.
+// FP64 rows -> FP32 storage of their BF16 roundings (round to nearest even)
+__global__ void k_store_rows_bf16(const double* __restrict__ T, int64_t n, float* __restrict__ dst) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t u = __float_as_uint((float)T[t]);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    dst[t] = __uint_as_float(u & 0xFFFF0000u);
+  }
+}
+
+// S[i][j] = (i == j) for i, j < n
+__global__ void k_set_eye(double* S, int ld, int n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t / n), j = (int)(t % n);
+  S[(int64_t)i * ld + j] = i == j ? 1.0 : 0.0;
+}
+
 __global__ void k_sym_update(double* H, int ld, const double* Hn, int nall, int n0, int nn) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)nall * nn) return;
@@ -284,6 +301,14 @@ DavidsonRun::DavidsonRun(risp_factors* f, const DavOptions& o, hipStream_t s) : 
   src_.alloc((size_t)block_ * sizeof(int));
   Hn_.alloc((size_t)cap_ * block_ * 8);
   split_.alloc((size_t)kDavSplit * cap_ * block_ * 8);
+  if (o.bf16_basis) {
+    RISP_CHECK(!fp64_, RISP_E_ARG, "a BF16-valued basis needs FP32 trial vectors");
+    S_.alloc((size_t)ld_ * ld_ * 8);
+    Ls_.alloc((size_t)cap_ * cap_ * 8);
+    Li_.alloc((size_t)cap_ * cap_ * 8);
+    T1_.alloc((size_t)cap_ * cap_ * 8);
+    Y_.alloc((size_t)ld_ * ld_ * 8);
+  }
   hnorm_.assign(block_, 0.0);
   htheta_.assign(ld_, 0.0);
 
@@ -346,6 +371,77 @@ void DavidsonRun::update_H(int nall, int n0, int nn) {
   gemm(g, split_.get(), s_);
   k_sym_update<<<ceil_div((int64_t)nall * nn, 256), 256, 0, s_>>>(H_.as<double>(), ld_, Hn_.as<double>(), nall, n0, nn);
   RISP_LAUNCHED();
+}
+
+// S rows / columns n0 .. n0 + nn of V^T V (bf16_basis)
+void DavidsonRun::update_S(int nall, int n0, int nn) {
+  Gemm g;
+  g.M = nall;
+  g.N = nn;
+  g.K = (int)ov_;
+  g.tin = DType::F64;
+  g.tout = DType::F64;
+  g.mem_a = tvec_;
+  g.mem_b = tvec_;
+  g.A = V_.get();
+  g.lda = ov_;
+  g.B = vrow(V_, n0);
+  g.ldb = ov_;
+  g.C = Hn_.get();
+  g.ldc = nn;
+  g.ksplit = std::min(kDavSplit, gemm_auto_split(g));
+  gemm(g, split_.get(), s_);
+  k_sym_update<<<ceil_div((int64_t)nall * nn, 256), 256, 0, s_>>>(S_.as<double>(), ld_, Hn_.as<double>(), nall, n0, nn);
+  RISP_LAUNCHED();
+}
+
+// Lowest kk pairs of H c = theta S c (H in Hw_): S = L L^T, L^-1 H L^-T y = theta y, c = L^-T y (Zs_)
+void DavidsonRun::generalized_eig(int kk) {
+  const int n = nsub_;
+  k_copy_sub<<<ceil_div((int64_t)n * n, 256), 256, 0, s_>>>(S_.as<double>(), ld_, n, Ls_.as<double>(), n);
+  RISP_LAUNCHED();
+  try {
+    cholesky(Ls_.as<double>(), n, s_);
+  } catch (const Error&) {
+    throw Error(RISP_E_STATE, "Davidson: the projected overlap of the BF16-valued basis is not positive definite");
+  }
+  tri_inverse(Ls_.as<double>(), Li_.as<double>(), n, s_);
+  Gemm g;  // T1 = H L^-T: T1[i][j] = sum_t H[i][t] Li[j][t]
+  g.M = n;
+  g.N = n;
+  g.K = n;
+  g.tin = g.tout = DType::F64;
+  g.A = Hw_.get();
+  g.lda = ld_;
+  g.B = Li_.get();
+  g.ldb = n;
+  g.C = T1_.get();
+  g.ldc = n;
+  gemm(g, nullptr, s_);
+  Gemm h = g;  // Hw = L^-1 T1: Hw[i][j] = sum_t Li[i][t] T1[t][j]
+  h.A = Li_.get();
+  h.lda = n;
+  h.B = T1_.get();
+  h.ldb = n;
+  h.b_kc = false;
+  h.C = Hw_.get();
+  h.ldc = ld_;
+  gemm(h, nullptr, s_);
+  subspace_eig(Hw_.as<double>(), n, ld_, kk, theta_.as<double>(), Y_.as<double>(), eigws_.as<double>(), s_);
+  Gemm z;  // Zs = L^-T Y: Zs[r][q] = sum_t Li[t][r] Y[t][q]
+  z.M = n;
+  z.N = kk;
+  z.K = n;
+  z.tin = z.tout = DType::F64;
+  z.A = Li_.get();
+  z.lda = n;
+  z.a_kc = false;
+  z.B = Y_.get();
+  z.ldb = ld_;
+  z.b_kc = false;
+  z.C = Zs_.get();
+  z.ldc = ld_;
+  gemm(z, nullptr, s_);
 }
 
 void DavidsonRun::row_norms(const double* R, int k, double* out_dev) {
@@ -448,6 +544,12 @@ void DavidsonRun::project_out(int nsub, int nt) {
 }
 
 void DavidsonRun::store_T(int r0, int n) {
+  if (o_.bf16_basis) {
+    k_store_rows_bf16<<<grid_for((int64_t)n * ov_), 256, 0, s_>>>(T_.as<double>(), (int64_t)n * ov_,
+                                                                  reinterpret_cast<float*>(vrow(V_, r0)));
+    RISP_LAUNCHED();
+    return;
+  }
   if (fp64_)
     k_store_rows<double><<<grid_for((int64_t)n * ov_), 256, 0, s_>>>(T_.as<double>(), (int64_t)n * ov_,
                                                                     reinterpret_cast<double*>(vrow(V_, r0)));
@@ -466,8 +568,10 @@ void DavidsonRun::complete() {
   if (state_ == State::Init) {
     nsub_ = rq_.n;
     update_H(nsub_, 0, nsub_);
+    if (o_.bf16_basis) update_S(nsub_, 0, nsub_);
   } else if (state_ == State::Append) {
     update_H(nsub_ + rq_.n, nsub_, rq_.n);
+    if (o_.bf16_basis) update_S(nsub_ + rq_.n, nsub_, rq_.n);
     nsub_ += rq_.n;
   }
   iterate(tsub);
@@ -504,7 +608,8 @@ void DavidsonRun::iterate(Timer& tsub) {
   const int k = std::min(block_, nsub_);
   // Ritz pairs kept by a thick restart; computed only when this iteration may restart
   const int kk = nsub_ + block_ > max_space_ ? std::min(2 * block_, nsub_) : k;
-  subspace_eig(Hw_.as<double>(), nsub_, ld_, kk, theta_.as<double>(), Zs_.as<double>(), eigws_.as<double>(), s_);
+  if (o_.bf16_basis) generalized_eig(kk);
+  else subspace_eig(Hw_.as<double>(), nsub_, ld_, kk, theta_.as<double>(), Zs_.as<double>(), eigws_.as<double>(), s_);
   combine_rows(Zs_.as<double>(), ld_, nsub_, k, V_.get(), X, 1.0, 0.0);
   combine_rows(Zs_.as<double>(), ld_, nsub_, k, W_.get(), AX_.as<double>(), 1.0, 0.0);
   k_residual<<<grid_for((int64_t)k * ov), 256, 0, s_>>>(AX_.as<double>(), X, theta_.as<double>(), k, ov);
@@ -602,6 +707,10 @@ void DavidsonRun::thick_restart(int keep) {
   RISP_HIP(hipMemcpyAsync(W_.get(), Rw_.get(), bytes, hipMemcpyDefault, s_));
   k_diag_H<<<ceil_div((int64_t)keep * keep, 256), 256, 0, s_>>>(H_.as<double>(), ld_, keep, theta_.as<double>());
   RISP_LAUNCHED();
+  if (o_.bf16_basis) {  // V Z is S-orthonormal: Z^T S Z = I
+    k_set_eye<<<ceil_div((int64_t)keep * keep, 256), 256, 0, s_>>>(S_.as<double>(), ld_, keep);
+    RISP_LAUNCHED();
+  }
   nsub_ = keep;
 }
 

@@ -37,6 +37,10 @@ struct DavOptions {
   // Olsen's correction t = (D - theta)^-1 (r - eps x) with eps such that t is orthogonal to x (D the
   // diagonal of A); false: t = (D - theta)^-1 r
   bool olsen = false;
+  // rows stored for a product are rounded to BF16 values (FP32 trial vectors only), so split-BF16
+  // products can skip the vector's lo half; the basis is then orthonormal only to about 2^-9 and the
+  // Rayleigh-Ritz solves H c = theta S c with the projected overlap S = V^T V
+  bool bf16_basis = false;
 };
 
 struct DavResult {
@@ -64,12 +68,15 @@ class DavidsonRun {
   bool next(Request& rq) const;  // false when finished
   void complete();
   bool done() const { return state_ == State::Done; }
+  bool bf16_basis() const { return o_.bf16_basis; }
   DavResult& result() { return res_; }
 
  private:
   enum class State { Init, Append, Done };
   void* vrow(DevBuf& b, int r);
   void update_H(int nall, int n0, int nn);
+  void update_S(int nall, int n0, int nn);
+  void generalized_eig(int kk);
   void row_norms(const double* R, int k, double* out_dev);
   void combine_rows(const double* Cm, int ldcm, int nsub, int k, const void* Vsrc, double* out, double alpha,
                     double beta);
@@ -98,6 +105,7 @@ class DavidsonRun {
   std::vector<double> hnorm_, htheta_;
   DevBuf V_, W_, H_, Hw_, Zs_, eigws_, theta_, AX_, T_, T2_, Cmix_, G_, Cf_, partial_, norms_, eps_, kept_,
       src_, Hn_, split_, Rv_, Rw_;
+  DevBuf S_, Ls_, Li_, T1_, Y_;  // bf16_basis: overlap, its Cholesky factor and inverse, products
 };
 
 void davidson(risp_factors* f, const DavOptions& o, const SigmaFn& sigma_fn, DavResult& res);

@@ -1170,7 +1170,7 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
 
 // coulomb_only: stop after the Coulomb term (sig = 2 J X, no diagonal, no exchange)
 static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s, const SigmaWs& w,
-                      bool coulomb_only = false) {
+                      bool coulomb_only = false, bool x_bf16 = false) {
   const bool bf = f->precision == RISP_BF16 && !use_f32;
   const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
   const DType tv = f->precision == RISP_FP64 ? DType::F64 : DType::F32;  // X / sigma type
@@ -1343,8 +1343,9 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
       g1.sc_outer = (int64_t)nvk * np * nokp;
       g1.batch_scale = (bf || split) ? f->scale_k.as<float>() + P0 : nullptr;
       if (split) {
-        // (hi, hi) + (lo, hi) + (hi, lo) in one accumulation; the intermediate as hi + lo halves
-        g1.npair = 3;
+        // (hi, hi) + (lo, hi) + (hi, lo) in one accumulation; the intermediate as hi + lo halves (BF16
+        // valued X: its lo block is zero and the third pair is left out)
+        g1.npair = x_bf16 ? 2 : 3;
         g1.A2 = static_cast<const uint16_t*>(f->t_ab_lo.get()) + (size_t)P0 * nvk * nvkp;
         g1.A3 = g1.A;
         g1.B2 = g1.B;
@@ -1393,7 +1394,7 @@ static void sigma_run(risp_factors* f, int m, const void* X, void* sig, bool use
 }
 
 
-void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s) {
+void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s, bool x_bf16) {
   if (m <= 0) return;
   const bool bf = f->precision == RISP_BF16 && !use_f32;
   const DType tc = f->precision == RISP_FP64 ? DType::F64 : (bf ? DType::BF16 : DType::F32);
@@ -1406,7 +1407,7 @@ void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipSt
   w.mt = {f->ws_mt.get(), f->ws_mt.bytes()};
   w.k = {f->ws_k.get(), f->ws_k.bytes()};
   w.split = {f->ws_split.get(), f->ws_split.bytes()};
-  sigma_run(f, m, X, sig, use_f32, s, w);
+  sigma_run(f, m, X, sig, use_f32, s, w, false, x_bf16 && use_f32);
 }
 
 // P = A V + 2 J V - KB V and M = A V - 2 J V + KB V, where on entry P holds A V and M holds 2 J V

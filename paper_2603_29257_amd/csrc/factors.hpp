@@ -105,8 +105,9 @@ constexpr int kAoMaxNao = 16384;
 // accumulation; `use_f32` selects the correction-pass arithmetic of BF16 factors: the Coulomb term
 // from the FP32 copy of T_ia and the exchange from split BF16 operands (factor and vector each as
 // hi + lo BF16 parts, three BF16 products per contraction, FP32 accumulation, the intermediate kept
-// as hi + lo), about 2^-16 relative.
-void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s);
+// as hi + lo), about 2^-16 relative. x_bf16 (with use_f32): every element of X is a BF16 value, so
+// the vector's lo part is zero and the first exchange contraction skips its (hi, lo) product.
+void sigma(risp_factors* f, int m, const void* X, void* sig, bool use_f32, hipStream_t s, bool x_bf16 = false);
 
 // sigma in the stored precision with every workspace taken from [scratch, scratch + cap): no
 // allocation. Throws RISP_E_SHAPE when m vectors do not fit (sigma_scratch_need gives the bytes of

@@ -556,7 +556,10 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
       oc.nx0 = r.krows;
       oc.max_iter = 1 + (opts->correction_steps > 0 ? opts->correction_steps : 16);
       oc.max_corr = opts->correction_ncorr > 0 ? opts->correction_ncorr : opts->nstates;
-      SigmaFn f32 = [&](int m, const void* X, void* S) { sigma(f, m, X, S, true, s); };
+      // BF16-valued basis rows: the split products skip the vector's lo half
+      oc.bf16_basis = (opts->flags & RISP_DAV_FP32_BASIS) == 0;
+      const bool xb = oc.bf16_basis;
+      SigmaFn f32 = [&](int m, const void* X, void* S) { sigma(f, m, X, S, true, s, xb); };
       davidson(f, oc, f32, rc);
       corr_iters = rc.iters;
       t_corr = seconds_since(t0);

@@ -247,7 +247,8 @@ void Server::tick() {
       for (size_t k = 0; k < launched.size(); ++k) {
         Job& j = *launched[k];
         RISP_HIP(hipStreamWaitEvent(j.stream, fork, 0));
-        sigma(j.F.get(), reqs[k].n, reqs[k].X, reqs[k].S, j.stage == 1, j.stream);
+        sigma(j.F.get(), reqs[k].n, reqs[k].X, reqs[k].S, j.stage == 1, j.stream,
+              j.stage == 1 && j.run->bf16_basis());
         RISP_HIP(hipEventRecord(joins[k], j.stream));
         RISP_HIP(hipStreamWaitEvent(ts, joins[k], 0));
       }
@@ -278,7 +279,8 @@ void Server::tick() {
       Job& j = *launched[k];
       j.sigma_timer = Timer();
       if (j.t_first_sigma < 0) j.t_first_sigma = now_s(t0);
-      sigma(j.F.get(), reqs[k].n, reqs[k].X, reqs[k].S, j.stage == 1, j.stream);
+      sigma(j.F.get(), reqs[k].n, reqs[k].X, reqs[k].S, j.stage == 1, j.stream,
+            j.stage == 1 && j.run->bf16_basis());
     }
   }
   // subspace steps
@@ -356,6 +358,7 @@ void Server::loop() {
             oc.max_corr = j.opts.correction_ncorr > 0 ? j.opts.correction_ncorr : j.opts.nstates;
             oc.spill = (j.opts.flags & RISP_DAV_SPILL) != 0;
             oc.olsen = (j.opts.flags & RISP_DAV_OLSEN) != 0;
+            oc.bf16_basis = (j.opts.flags & RISP_DAV_FP32_BASIS) == 0;
             oc.max_space = j.opts.max_space;
             oc.tol = j.opts.tol;
             oc.x0_dev = j.main_res.X.as<double>();

@@ -484,3 +484,20 @@ def test_davidson_olsen_energies_config0(ctx, mol0, oracle0, prec):
     assert info.converged
     assert np.abs(e - w).max() <= (1e-6 if prec == "fp32" else 2e-5)
     F.free()
+
+
+def test_davidson_bf16_correction_basis_both_ways(ctx, mol0, oracle0):
+    # the BF16 correction pass with BF16-valued basis vectors (the default: two split products in the
+    # first exchange contraction, Rayleigh-Ritz with the basis overlap) and with FP32 basis vectors
+    # (RISP_DAV_FP32_BASIS): both reach the oracle's energies and agree with each other
+    import paper_2603_29257_amd as P
+    w, _ = R.lowest_eigh(R.dense_A(oracle0), 5)
+    F = _gpu_factors(ctx, mol0, precision=P.BF16)
+    ea, _, ia = ctx.davidson(F, 5, tol=1e-5)
+    eb, _, ib = ctx.davidson(F, 5, tol=1e-5, fp32_basis=True)
+    _print(f"bf16 correction basis: BF16-valued {ia.correction_iters} steps, FP32 {ib.correction_iters} steps, "
+           f"|dE| {np.abs(ea - w).max():.2e} / {np.abs(eb - w).max():.2e}")
+    assert ia.converged and ib.converged
+    assert np.abs(ea - w).max() <= 2e-5 and np.abs(eb - w).max() <= 2e-5
+    assert np.abs(ea - eb).max() <= 1e-6
+    F.free()
