@@ -157,8 +157,25 @@ static void metric_apply_inplace(const double* Linv, int n, double* T, int64_t c
   if (n == 0 || cols == 0) return;
   const int64_t w = metric_panel_cols(n, cols);
   RISP_CHECK(tmp.bytes() >= (size_t)n * w * 8, RISP_E_STATE, "metric panel buffer too small");
+  // each panel transposed to [col][Q] (contraction-contiguous), then T[:, panel] = L^-1 panel on
+  // the NT MFMA kernel straight into T; an odd n (no 16-byte contraction rows) keeps the generic form
+  Gemm nt = g64(n, (int)std::min<int64_t>(w, cols), n);
+  nt.A = Linv;
+  nt.lda = n;
+  nt.B = tmp.get();
+  nt.ldb = n;
+  nt.C = T;
+  nt.ldc = cols;
+  const bool use_nt = gemm_bf16_nt_eligible(nt);
   for (int64_t c0 = 0; c0 < cols; c0 += w) {
     const int nc = (int)std::min<int64_t>(w, cols - c0);
+    if (use_nt) {
+      transpose64(T + c0, cols, n, nc, tmp.as<double>(), n, s);
+      nt.N = nc;
+      nt.C = T + c0;
+      gemm(nt, nullptr, s);
+      continue;
+    }
     Gemm g = g64(n, nc, n);
     g.A = Linv;
     g.lda = n;

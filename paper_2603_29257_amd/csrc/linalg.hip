@@ -316,6 +316,31 @@ void store_block(const void* src, DType ts, int64_t lds, int64_t sps, void* dst,
   RISP_LAUNCHED();
 }
 
+// out[c][r] = A[r][c] for r < rows, c < cols (FP64; A row stride lda, out row stride ldo), through
+// 32 x 32 tiles in LDS so both the reads and the writes are coalesced
+__global__ __launch_bounds__(256) void k_transpose64(const double* __restrict__ A, int64_t lda, int rows, int cols,
+                                                     double* __restrict__ out, int64_t ldo) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = A[(int64_t)r * lda + c];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (c < cols && r < rows) out[(int64_t)c * ldo + r] = tile[tx][k];
+  }
+}
+
+void transpose64(const double* A, int64_t lda, int rows, int cols, double* out, int64_t ldo, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  RISP_CHECK(ceil_div(rows, 32) <= 65535, RISP_E_SHAPE, "transpose64: too many rows");
+  k_transpose64<<<dim3(ceil_div(cols, 32), ceil_div(rows, 32)), 256, 0, s>>>(A, lda, rows, cols, out, ldo);
+  RISP_LAUNCHED();
+}
+
 // FP64 block -> FP32 values kept as their upper and lower 16-bit halves in two arrays (the two BF16
 // arrays of a split factor used as FP32 staging), same indexing as k_store_block
 __global__ void k_store_block_split(const double* __restrict__ src, int64_t lds, int64_t sps, uint16_t* __restrict__ hi,

@@ -44,6 +44,9 @@ void pow2_from_max(const double* mx, int n, bool enabled, float* scale, hipStrea
 void store_block(const void* src, DType ts, int64_t lds, int64_t sps, void* dst, DType td, int64_t ldd, int64_t dps,
                  int64_t np, int64_t nr, int64_t nc, hipStream_t s);
 
+// out[c][r] = A[r][c] (FP64), rows x cols, row strides lda and ldo
+void transpose64(const double* A, int64_t lda, int rows, int cols, double* out, int64_t ldo, hipStream_t s);
+
 // store_block of an FP64 source into FP32 values kept as upper / lower 16-bit halves in hi and lo
 void store_block_split(const double* src, int64_t lds, int64_t sps, void* hi, void* lo, int64_t ldd, int64_t dps,
                        int64_t np, int64_t nr, int64_t nc, hipStream_t s);
