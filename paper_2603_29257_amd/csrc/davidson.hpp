@@ -18,6 +18,9 @@ struct Timer {
 // factors, FP32 otherwise). Must be stream-ordered on the context stream.
 using SigmaFn = std::function<void(int m, const void* X, void* S)>;
 
+// default tolerance of the BF16 stage before the correction pass of BF16 factors
+constexpr double kBf16StageTol = 1e-3;
+
 struct DavOptions {
   int nstates = 5;
   int block = 0;

@@ -535,7 +535,7 @@ risp_status risp_davidson(risp_ctx* ctx, const risp_factors* fc, const risp_dav_
     DavOptions ob = o;
     if (f->precision == RISP_BF16) {
       // BF16 products bound the attainable residual: stop at the stage tolerance or on a stall
-      const double bt = opts->bf16_tol > 0.0 ? opts->bf16_tol : 1e-4;
+      const double bt = opts->bf16_tol > 0.0 ? opts->bf16_tol : kBf16StageTol;
       if (correct) ob.tol = std::max(o.tol, bt);
       ob.stall_iters = 2;
       ob.stall_below = 10.0 * bt;

@@ -163,9 +163,9 @@ void Server::admit(Job& j) {
   o.spill = (j.opts.flags & RISP_DAV_SPILL) != 0;
   o.olsen = (j.opts.flags & RISP_DAV_OLSEN) != 0;
   if (j.prm.precision == RISP_BF16) {
-    if (j.opts.correction_pass) o.tol = std::max(o.tol, j.opts.bf16_tol > 0.0 ? j.opts.bf16_tol : 1e-4);
+    if (j.opts.correction_pass) o.tol = std::max(o.tol, j.opts.bf16_tol > 0.0 ? j.opts.bf16_tol : kBf16StageTol);
     o.stall_iters = 2;
-    o.stall_below = 10.0 * (j.opts.bf16_tol > 0.0 ? j.opts.bf16_tol : 1e-4);
+    o.stall_below = 10.0 * (j.opts.bf16_tol > 0.0 ? j.opts.bf16_tol : kBf16StageTol);
   }
   j.run = std::make_unique<DavidsonRun>(j.F.get(), o, j.stream);
   j.stage = 0;

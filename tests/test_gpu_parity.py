@@ -426,11 +426,12 @@ def test_ao_route_rejected_by_serving(ctx, mol0):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_davidson_spilled_subspace_identical(ctx, mol0, prec):
-    # the subspace in pinned host memory runs the same kernels on the same values
+    # the subspace in pinned host memory runs the same kernels on the same values (a BF16 stage
+    # tolerance of 1e-4 keeps that stage long enough to restart in a subspace of 40)
     import paper_2603_29257_amd as P
     F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec])
-    e1, v1, i1 = ctx.davidson(F, 5, tol=1e-5, max_space=40)
-    e2, v2, i2 = ctx.davidson(F, 5, tol=1e-5, max_space=40, spill=True)
+    e1, v1, i1 = ctx.davidson(F, 5, tol=1e-5, max_space=40, bf16_tol=1e-4)
+    e2, v2, i2 = ctx.davidson(F, 5, tol=1e-5, max_space=40, spill=True, bf16_tol=1e-4)
     assert i1.restarts > 0 and i1.iters == i2.iters
     assert np.array_equal(e1, e2) and np.array_equal(v1, v2)
     F.free()
