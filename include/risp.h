@@ -54,9 +54,10 @@ enum { RISP_FP64 = 0, RISP_FP32 = 1, RISP_BF16 = 2 };
  * forms the AO transition densities D_m = C_occ X_m C_vir^T, contracts them with (mu nu|Q)
  * regenerated over the screened pairs, applies the inverse metric, contracts back with (mu nu|P)
  * regenerated again and transforms J_m = C_occ^T U_m C_vir, all in FP64; for molecules whose T_ia
- * does not fit in device memory. The AO transition densities are dense FP64 [nao][nao] slices, so
- * the route takes nao <= 16384. Served jobs take RISP_J_MO only (the route synchronises inside
- * sigma and cannot run in the serving loop's graphs). */
+ * does not fit in device memory. The integrals are regenerated in a packed layout over the kept
+ * pairs (per-atom partner lists), so only the AO densities of a group of trial vectors are dense
+ * FP64 [nao][nao]. Served jobs take RISP_J_MO only (the route synchronises inside sigma and cannot
+ * run in the serving loop's graphs). */
 enum { RISP_J_MO = 0, RISP_J_AO_DIRECT = 1 };
 /* reading of the range-separated exchange: one RI in the J^ metric (paper eq. K_mia_RSH) or
  * alpha RI(1/r) + beta RI(erf) stacked along the auxiliary index */

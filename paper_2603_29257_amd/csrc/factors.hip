@@ -20,7 +20,7 @@ int64_t risp_factors::bytes() const {
                    ws_y.bytes() + ws_ybf.bytes() + ws_xbf.bytes() + ws_xw.bytes() + ws_mt.bytes() +
                    ws_k.bytes() + ws_split.bytes() + shell_bytes(ao_sh) + shell_bytes(auxj_sh) + pairs.a.bytes() +
                    pairs.b.bytes() + linv_j.bytes() + co_t.bytes() + cv_t.bytes() + ws_ao_t.bytes() +
-                   ws_ao_d.bytes() + ws_ao_v.bytes() + ws_ao_r.bytes());
+                   ws_ao_d.bytes() + ws_ao_v.bytes() + ws_ao_r.bytes() + ws_ao_p.bytes());
 }
 
 void risp_ctx::resolve_phases() {
@@ -272,33 +272,6 @@ static void transformed_3c(risp_ctx* ctx, hipStream_t s, const DevShells& ao, co
   RISP_HIP(hipStreamSynchronize(s));
 }
 
-// Per-atom partner lists of the kept shell pairs: the first transform G[P][i][mu] =
-// sum_nu C[i][nu] (mu nu|P) only needs, for the functions mu of one atom, the functions nu that
-// form a kept pair with one of that atom's shells (on the 1000-atom molecule 14.5 % of nao^2 instead
-// of every nu), so it runs as one small dense product per atom over its partners.
-struct Partners {
-  int ngroups = 0;
-  int64_t S = 0;   // elements of one auxiliary function in the packed layout: sum_g n_g kp_g
-  std::vector<int> mu0, n, kp;
-  std::vector<int64_t> voff, koff;  // per group: sum over earlier groups of n kp, of kp
-  DevBuf idx;                       // [sum kp] partner functions, -1 = padding
-  DevBuf gkoff, gkp;                // per group (device copies of koff, kp)
-  DevBuf fvoff, fng, fkp, fml;      // per AO function: its group's voff, n, kp, and its index in the group
-  DevBuf cab, cba;                  // per kept pair (device list order), see PackMap
-  PackMap map(int nf_stride) const {
-    PackMap m;
-    m.voff = fvoff.as<int64_t>();
-    m.ng = fng.as<int>();
-    m.kp = fkp.as<int>();
-    m.ml = fml.as<int>();
-    m.cab = cab.as<int>();
-    m.cba = cba.as<int>();
-    m.nf_stride = nf_stride;
-    m.elems = (int64_t)nf_stride * S;
-    return m;
-  }
-};
-
 static void build_partners(const risp_system* sys, const PairList& pairs, Partners& P, hipStream_t s) {
   const int nsh = sys->nshell;
   std::vector<int> shoff(nsh + 1, 0);
@@ -367,6 +340,15 @@ static void build_partners(const risp_system* sys, const PairList& pairs, Partne
     RISP_CHECK(it != pl.end() && *it == t, RISP_E_STATE, "partner list misses a kept pair");
     return spos[g][it - pl.begin()];
   };
+  // row and partner function of every packed position (group, mu, k) of one auxiliary function
+  std::vector<int> hrow((size_t)P.S), hcol((size_t)P.S);
+  for (int g = 0; g < ng; ++g)
+    for (int ml = 0; ml < P.n[g]; ++ml)
+      for (int k = 0; k < P.kp[g]; ++k) {
+        const size_t q = (size_t)P.voff[g] + (size_t)ml * P.kp[g] + k;
+        hrow[q] = P.mu0[g] + ml;
+        hcol[q] = hidx[(size_t)P.koff[g] + k];
+      }
   std::vector<int> hcab(pairs.n), hcba(pairs.n);
   for (int ip = 0; ip < pairs.n; ++ip) {
     hcab[ip] = where(gsh[pa[ip]], pb[ip]);
@@ -381,6 +363,8 @@ static void build_partners(const risp_system* sys, const PairList& pairs, Partne
   P.fml = upload(hfml.data(), hfml.size(), s);
   P.cab = upload(hcab.data(), hcab.size(), s);
   P.cba = upload(hcba.data(), hcba.size(), s);
+  P.prow = upload(hrow.data(), hrow.size(), s);
+  P.pcol = upload(hcol.data(), hcol.size(), s);
   RISP_HIP(hipStreamSynchronize(s));  // the host arrays die at return
 }
 
@@ -584,8 +568,6 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
              "theta must be positive, tau and omega non-negative");
   RISP_CHECK(prm->beta == 0.0 || prm->omega > 0.0, RISP_E_ARG, "beta != 0 needs omega > 0");
   RISP_CHECK(prm->j_mode == RISP_J_MO || prm->j_mode == RISP_J_AO_DIRECT, RISP_E_ARG, "bad j_mode");
-  RISP_CHECK(prm->j_mode == RISP_J_MO || sys->nao <= kAoMaxNao, RISP_E_SHAPE,
-             "the AO Coulomb route takes nao <= " + std::to_string(kAoMaxNao));
   RISP_CHECK(!prm->full_tddft || (prm->precision != RISP_BF16 && prm->rsh_mode == RISP_RSH_COMBINED &&
                                    prm->j_mode == RISP_J_MO),
              RISP_E_ARG, "full TDDFT-risp factors: FP64 or FP32 storage, combined exchange, stored Coulomb route");
@@ -635,7 +617,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   // first transforms over the per-atom partner lists of the kept pairs, or over dense slabs
   Partners partners;
   const bool sparse_t = prm->dense_transform == 0;
-  if (sparse_t) build_partners(sys, pairs, partners, s);
+  if (sparse_t || prm->j_mode == RISP_J_AO_DIRECT) build_partners(sys, pairs, partners, s);
   Arena ar;
   auto t3c = [&](const DevShells& aux, const Operator& op, const double* CLT, int nl, const double* CRT, int nr,
                  double* out) {
@@ -766,11 +748,11 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   // place, then stored rows.
   if (!jmo) {
     // no stored T_ia: keep the metric factor and plan the auxiliary chunks of the per-sigma integral
-    // passes (dense (mu nu|P) slices of at most ~2 GiB, whole shells)
+    // passes (packed (mu nu|P) over the kept pairs, at most ~2 GiB per chunk, whole shells)
     Operator coul;
     metric_inverse_cholesky(ctx, s, aj, coul, f->linv_j);
     f->j_op = coul;
-    const int64_t per_func = (int64_t)nao * nao * 8;
+    const int64_t per_func = std::max<int64_t>(partners.S * 8, 8);
     const int max_f = (int)std::max<int64_t>(3, std::min<int64_t>(256, (2ll << 30) / per_func));
     const int ns = (int)auxJ.size();
     f->ao_s0.clear();
@@ -789,8 +771,8 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     f->ao_s0.push_back(ns);
     f->ao_f0.push_back(fo);
     RISP_CHECK(fo == aj.nfunc, RISP_E_STATE, "auxiliary chunk plan does not cover the basis");
-    // trial vectors per group: D_m and U_m slices within 4 GiB
-    f->ao_mg = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4ll << 30) / per_func));
+    // trial vectors per group: dense D_m and U_m slices within 4 GiB
+    f->ao_mg = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4ll << 30) / ((int64_t)nao * nao * 8)));
   } else {
     Operator coul;  // 1/r
     DevBuf Linv;
@@ -948,6 +930,7 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     f->pairs = std::move(pairs);
     f->co_t = std::move(CoT);
     f->cv_t = std::move(CvT);
+    f->ao_partners = std::move(partners);
   }
 }
 
@@ -991,10 +974,11 @@ static void ensure_workspace(risp_factors* f, int m, DType tc, hipStream_t s) {
   const size_t acc = cs == 8 ? 8 : 4;
   size_t split_bytes = 0;
   if (f->j_mode == RISP_J_AO_DIRECT) {
-    const size_t mg = std::min(m, f->ao_mg), nao = f->nao;
+    const size_t mg = std::min(m, f->ao_mg), nao = f->nao, S = (size_t)f->ao_partners.S;
     f->ws_ao_t.alloc(mg * f->nocc * nao * 8);
     f->ws_ao_d.alloc(mg * nao * nao * 8);
-    f->ws_ao_v.alloc((size_t)f->ao_max_f * nao * nao * 8);
+    f->ws_ao_v.alloc((size_t)f->ao_max_f * S * 8);
+    f->ws_ao_p.alloc(mg * S * 8);
     f->ws_ao_r.alloc(2 * (size_t)f->naux_j * mg * 8);
     split_bytes = (size_t)kMaxSplit * f->ao_max_f * mg * 8;
   } else {
@@ -1043,6 +1027,34 @@ struct SigmaWs {
   int64_t mt_budget = kMtBudget;
 };
 
+static unsigned grid_1d(int64_t n) { return (unsigned)std::min<int64_t>(ceil_div(n, 256), 1 << 16); }
+
+// Dp[m][q] = D[m][prow[q]][pcol[q]] (0 for padding): dense AO matrices gathered into the packed
+// order of one auxiliary function's integrals
+__global__ void k_pack_dense(const double* __restrict__ D, int nao, const int* __restrict__ prow,
+                             const int* __restrict__ pcol, int64_t S, int mg, double* __restrict__ Dp) {
+  const int64_t n2 = (int64_t)nao * nao, total = (int64_t)mg * S;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(t / S);
+    const int64_t q = t % S;
+    const int nu = pcol[q];
+    Dp[t] = nu >= 0 ? D[m * n2 + (int64_t)prow[q] * nao + nu] : 0.0;
+  }
+}
+
+// U[m][prow[q]][pcol[q]] = Up[m][q] for the packed positions that hold a pair; every kept pair (mu, nu)
+// has exactly one position (in mu's group), the other elements of U are zero beforehand
+__global__ void k_unpack_dense(const double* __restrict__ Up, int nao, const int* __restrict__ prow,
+                               const int* __restrict__ pcol, int64_t S, int mg, double* __restrict__ U) {
+  const int64_t n2 = (int64_t)nao * nao, total = (int64_t)mg * S;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(t / S);
+    const int64_t q = t % S;
+    const int nu = pcol[q];
+    if (nu >= 0) U[m * n2 + (int64_t)prow[q] * nao + nu] = Up[t];
+  }
+}
+
 // Coulomb term by the AO-density route (section on on-the-fly Coulomb evaluation), FP64 throughout,
 // for groups of mg trial vectors:
 //   D_m = C_occ X_m C_vir^T;  R_Q = sum_(mu nu) (mu nu|Q) D_m,mu nu;  R~ = L^-T L^-1 R;
@@ -1057,8 +1069,12 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
   const int mgmax = std::min(m, f->ao_mg);
   need(f->ws_ao_t, (size_t)mgmax * nocc * nao * 8, "AO half-transformed block");
   need(f->ws_ao_d, (size_t)mgmax * n2 * 8, "AO densities");
-  need(f->ws_ao_v, (size_t)f->ao_max_f * n2 * 8, "AO integral chunk");
+  const Partners& pk = f->ao_partners;
+  const int64_t S = pk.S;
+  need(f->ws_ao_v, (size_t)f->ao_max_f * S * 8, "AO integral chunk");
+  need(f->ws_ao_p, (size_t)mgmax * S * 8, "packed AO densities");
   need(f->ws_ao_r, 2 * (size_t)nJ * mgmax * 8, "AO auxiliary vectors");
+  double* Dp = f->ws_ao_p.as<double>();  // packed D_m in pass 1, packed U_m in pass 2
   double* G = f->ws_ao_t.as<double>();
   double* D = f->ws_ao_d.as<double>();  // D_m in pass 1, U_m in pass 2
   double* V = f->ws_ao_v.as<double>();
@@ -1069,8 +1085,8 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
     const int mg = std::min(mgmax, m - g0);
     {
       PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y,
-                    2.0 * mg * ((double)ov * nao + (double)nocc * n2 + (double)nJ * n2 + 2.0 * nJ * nJ),
-                    (double)vsz * mg * ov + 8.0 * ((double)nJ * n2 + 2.0 * mg * n2 + (double)nJ * nJ));
+                    2.0 * mg * ((double)ov * nao + (double)nocc * n2 + (double)nJ * S + 2.0 * nJ * nJ),
+                    (double)vsz * mg * ov + 8.0 * ((double)nJ * S + 2.0 * mg * S + mg * n2 + (double)nJ * nJ));
       // G[m][i][nu] = sum_a X[m][i][a] C_vir[nu][a]
       Gemm a = g64(nocc, nao, nvir);
       a.mem_a = tv;
@@ -1099,16 +1115,22 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
       b.sc2 = n2;
       b.nb2 = mg;
       gemm(b, nullptr, s);
-      // R[Q][m] = sum_(mu nu) (mu nu|Q) D[m][mu nu], chunk by chunk
+      // D_m in the packed order of the integrals (each kept pair (mu, nu) once per orientation)
+      k_pack_dense<<<grid_1d((int64_t)mg * S), 256, 0, s>>>(D, nao, pk.prow.as<int>(), pk.pcol.as<int>(), S, mg,
+                                                          Dp);
+      RISP_LAUNCHED();
+      // R[Q][m] = sum_(mu nu) (mu nu|Q) D[m][mu nu] over the kept pairs, chunk by chunk
       for (int c = 0; c < nchunk; ++c) {
         const int nf = f->ao_f0[c + 1] - f->ao_f0[c];
-        int3c(f->ao_sh, f->pairs, f->auxj_sh, f->ao_s0[c], f->ao_s0[c + 1], f->j_op, f->ctx->boys.as<double>(), V,
-              s);
-        Gemm r = g64(nf, mg, (int)n2);
+        const PackMap pm = pk.map_fmajor(nf);
+        int3c(f->ao_sh, f->pairs, f->auxj_sh, f->ao_s0[c], f->ao_s0[c + 1], f->j_op, f->ctx->boys.as<double>(), V, s,
+              &pm);
+        Gemm r = g64(nf, mg, (int)std::min<int64_t>(S, INT32_MAX));
+        RISP_CHECK(S < INT32_MAX, RISP_E_SHAPE, "packed integrals of one auxiliary function exceed 2^31 elements");
         r.A = V;
-        r.lda = n2;
-        r.B = D;
-        r.ldb = n2;
+        r.lda = S;
+        r.B = Dp;
+        r.ldb = S;
         r.C = R + (size_t)f->ao_f0[c] * mg;
         r.ldc = mg;
         r.ksplit = std::min(kMaxSplit, gemm_auto_split(r));
@@ -1137,24 +1159,31 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
       gemm(l2, nullptr, s);
     }
     PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_J,
-                  2.0 * mg * ((double)nJ * n2 + (double)nocc * n2 + (double)ov * nao),
-                  8.0 * ((double)nJ * n2 + 2.0 * mg * n2) + (double)vsz * mg * ov);
-    // U[m][mu nu] = sum_P R~[P][m] (mu nu|P), chunk by chunk (U overwrites D)
+                  2.0 * mg * ((double)nJ * S + (double)nocc * n2 + (double)ov * nao),
+                  8.0 * ((double)nJ * S + 2.0 * mg * S + mg * n2) + (double)vsz * mg * ov);
+    // U[m][mu nu] = sum_P R~[P][m] (mu nu|P) over the kept pairs, chunk by chunk in the packed order,
+    // then into the dense U (which overwrites D; the screened-out elements are zero)
     for (int c = 0; c < nchunk; ++c) {
       const int nf = f->ao_f0[c + 1] - f->ao_f0[c];
-      int3c(f->ao_sh, f->pairs, f->auxj_sh, f->ao_s0[c], f->ao_s0[c + 1], f->j_op, f->ctx->boys.as<double>(), V, s);
-      Gemm u = g64(mg, (int)n2, nf);
+      const PackMap pm = pk.map_fmajor(nf);
+      int3c(f->ao_sh, f->pairs, f->auxj_sh, f->ao_s0[c], f->ao_s0[c + 1], f->j_op, f->ctx->boys.as<double>(), V, s,
+            &pm);
+      Gemm u = g64(mg, (int)S, nf);
       u.A = R + (size_t)f->ao_f0[c] * mg;
       u.lda = mg;
       u.a_kc = false;
       u.B = V;
-      u.ldb = n2;
+      u.ldb = S;
       u.b_kc = false;
-      u.C = D;
-      u.ldc = n2;
+      u.C = Dp;
+      u.ldc = S;
       u.beta = c > 0 ? 1.0 : 0.0;
       gemm(u, nullptr, s);
     }
+    fill_zero(D, (size_t)mg * n2 * 8, s);
+    k_unpack_dense<<<grid_1d((int64_t)mg * S), 256, 0, s>>>(Dp, nao, pk.prow.as<int>(), pk.pcol.as<int>(), S, mg,
+                                                            D);
+    RISP_LAUNCHED();
     // H[m][i][nu] = sum_mu C_occ[mu][i] U[m][mu][nu]
     Gemm h = g64(nocc, nao, nao);
     h.A = f->co_t.get();

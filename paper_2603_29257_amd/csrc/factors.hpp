@@ -11,6 +11,42 @@ struct risp_factors;
 
 namespace risp {
 struct Server;
+// Per-atom partner lists of the kept shell pairs: the first transform G[P][i][mu] =
+// sum_nu C[i][nu] (mu nu|P) only needs, for the functions mu of one atom, the functions nu that
+// form a kept pair with one of that atom's shells (on the 1000-atom molecule 14.5 % of nao^2 instead
+// of every nu), so it runs as one small dense product per atom over its partners; the AO-density
+// Coulomb route contracts the integrals in the same packed layout.
+struct Partners {
+  int ngroups = 0;
+  int64_t S = 0;   // elements of one auxiliary function in the packed layout: sum_g n_g kp_g
+  std::vector<int> mu0, n, kp;
+  std::vector<int64_t> voff, koff;  // per group: sum over earlier groups of n kp, of kp
+  DevBuf idx;                       // [sum kp] partner functions, -1 = padding
+  DevBuf gkoff, gkp;                // per group (device copies of koff, kp)
+  DevBuf fvoff, fng, fkp, fml;      // per AO function: its group's voff, n, kp, and its index in the group
+  DevBuf cab, cba;                  // per kept pair (device list order), see PackMap
+  DevBuf prow, pcol;                // per packed position of one function: mu and nu (-1 = padding)
+  // group-major chunk [group][f][mu][partner] for nf_stride functions
+  PackMap map(int nf_stride) const {
+    PackMap m;
+    m.voff = fvoff.as<int64_t>();
+    m.ng = fng.as<int>();
+    m.kp = fkp.as<int>();
+    m.ml = fml.as<int>();
+    m.cab = cab.as<int>();
+    m.cba = cba.as<int>();
+    m.nf_stride = nf_stride;
+    m.elems = (int64_t)nf_stride * S;
+    return m;
+  }
+  // function-major chunk [f][group][mu][partner] (one contiguous row of S per function)
+  PackMap map_fmajor(int nf) const {
+    PackMap m = map(nf);
+    m.f_stride = S;
+    return m;
+  }
+};
+
 // Event-timed launches of one sigma phase.
 struct PhaseLog {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -90,8 +126,11 @@ struct risp_factors {
   std::vector<int> ao_s0, ao_f0;     // auxiliary shell / function start of each integral chunk (+ end)
   int ao_max_f = 0;                  // functions of the largest chunk
   int ao_mg = 0;                     // trial vectors per group (dense D_m / U_m slices)
-  // workspaces: G / H [ao_mg][nocc][nao], D / U [ao_mg][nao][nao], (mu nu|P) chunk, R and L^-1 R
+  // workspaces: G / H [ao_mg][nocc][nao], D / U [ao_mg][nao][nao], packed (mu nu|P) chunk [f][S],
+  // R and L^-1 R
   risp::DevBuf ws_ao_t, ws_ao_d, ws_ao_v, ws_ao_r;
+  risp::Partners ao_partners;  // packed layout of the regenerated integrals
+  risp::DevBuf ws_ao_p;        // D_m / U_m in the packed layout [ao_mg][S]
   double t_build = 0.0;  // seconds spent in the factor build
   int64_t bytes() const;
 };
@@ -99,7 +138,6 @@ struct risp_factors {
 namespace risp {
 
 // largest AO basis of the AO Coulomb route: one dense FP64 (mu nu|P) slice is at most 2 GiB
-constexpr int kAoMaxNao = 16384;
 
 // precision of the sigma arithmetic: FP64 factors -> FP64, FP32 -> FP32, BF16 -> BF16 with FP32
 // accumulation; `use_f32` selects the correction-pass arithmetic of BF16 factors: the Coulomb term

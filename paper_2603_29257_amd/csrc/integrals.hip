@@ -498,18 +498,26 @@ __global__ __launch_bounds__(256) void k_int3c(ShellView AO, ShellView AX, const
       // packed: row mu of A's group at column cab + kb, mirrored row nu of B's group at cba + ka
       const int fc = AX.off[C] - f0;
       const int cab = pk.cab[pair0 + ip], cba = pk.cba[pair0 + ip];
-      const int64_t ga = pk.nf_stride * pk.voff[oa], gb = pk.nf_stride * pk.voff[ob];
       const int nga = pk.ng[oa], ngb = pk.ng[ob], kpa = pk.kp[oa], kpb = pk.kp[ob];
       const int mla = pk.ml[oa], mlb = pk.ml[ob];
+      // offset of row (f, mu) for the first function mu of A's / B's shell: group-major or
+      // function-major layout
+      auto row_a = [&](int f) -> int64_t {
+        return pk.f_stride ? f * pk.f_stride + pk.voff[oa] + (int64_t)mla * kpa
+                           : pk.nf_stride * pk.voff[oa] + ((int64_t)f * nga + mla) * kpa;
+      };
+      auto row_b = [&](int f) -> int64_t {
+        return pk.f_stride ? f * pk.f_stride + pk.voff[ob] + (int64_t)mlb * kpb
+                           : pk.nf_stride * pk.voff[ob] + ((int64_t)f * ngb + mlb) * kpb;
+      };
       static_for<0, ncart(LA)>([&](auto ka) {
         static_for<0, ncart(LB)>([&](auto kb) {
           static_for<0, ncart(LC)>([&](auto kc) {
             const double v = os3c<LA, decltype(ka)::value, LB, decltype(kb)::value, LC,
                                   decltype(kc)::value>(c, AB) * nrm;
             const int f = fc + decltype(kc)::value;
-            out[ga + ((int64_t)f * nga + mla + decltype(ka)::value) * kpa + cab + decltype(kb)::value] = v;
-            if (!same)
-              out[gb + ((int64_t)f * ngb + mlb + decltype(kb)::value) * kpb + cba + decltype(ka)::value] = v;
+            out[row_a(f) + (int64_t)decltype(ka)::value * kpa + cab + decltype(kb)::value] = v;
+            if (!same) out[row_b(f) + (int64_t)decltype(kb)::value * kpb + cba + decltype(ka)::value] = v;
           });
         });
       });

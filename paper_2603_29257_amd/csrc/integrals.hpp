@@ -65,6 +65,9 @@ struct PackMap {
   const int* cba = nullptr;       // [npair] list position of A's first function in B's group
   int nf_stride = 0;
   int64_t elems = 0;              // elements of one chunk (nf_stride * sum_g n_g kp_g)
+  // > 0: function-major instead, element (f, mu, nu) at f * f_stride + voff[mu] + ml[mu] * kp[mu] +
+  // pos(nu) (f_stride = sum_g n_g kp_g: one contiguous row per auxiliary function)
+  int64_t f_stride = 0;
 };
 
 // (mu nu|P) with the given operator for auxiliary shells [s0, s1): out dev
