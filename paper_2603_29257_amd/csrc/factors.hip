@@ -19,7 +19,7 @@ int64_t risp_factors::bytes() const {
                    vir_k.bytes() + pos_o.bytes() + pos_v.bytes() + de64.bytes() + de32.bytes() + diag64.bytes() +
                    ws_y.bytes() + ws_ybf.bytes() + ws_xbf.bytes() + ws_xw.bytes() + ws_mt.bytes() +
                    ws_k.bytes() + ws_split.bytes() + shell_bytes(ao_sh) + shell_bytes(auxj_sh) + pairs.a.bytes() +
-                   pairs.b.bytes() + linv_j.bytes() + co_t.bytes() + cv_t.bytes() + ws_ao_t.bytes() +
+                   pairs.b.bytes() + linv_j.bytes() + co_t.bytes() + cv_t.bytes() + co.bytes() + ws_ao_t.bytes() +
                    ws_ao_d.bytes() + ws_ao_v.bytes() + ws_ao_r.bytes() + ws_ao_p.bytes());
 }
 
@@ -771,8 +771,12 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     f->ao_s0.push_back(ns);
     f->ao_f0.push_back(fo);
     RISP_CHECK(fo == aj.nfunc, RISP_E_STATE, "auxiliary chunk plan does not cover the basis");
-    // trial vectors per group: dense D_m and U_m slices within 4 GiB
-    f->ao_mg = (int)std::max<int64_t>(1, std::min<int64_t>(64, (4ll << 30) / ((int64_t)nao * nao * 8)));
+    // trial vectors per group (each group regenerates the integrals twice): as many as a quarter of
+    // the memory left after the factors holds (at least 4 GiB) with their dense D_m / U_m, packed
+    // D_m and half-transformed block; the rest stays for the Davidson subspace and the exchange
+    const int64_t per_vec = ((int64_t)nao * nao + (int64_t)nocc * nao + partners.S) * 8;
+    const int64_t ao_budget = std::max<int64_t>(4ll << 30, (int64_t)(fr / 4));
+    f->ao_mg = (int)std::max<int64_t>(1, std::min<int64_t>(64, ao_budget / per_vec));
   } else {
     Operator coul;  // 1/r
     DevBuf Linv;
@@ -930,6 +934,10 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
     f->pairs = std::move(pairs);
     f->co_t = std::move(CoT);
     f->cv_t = std::move(CvT);
+    f->co.alloc((size_t)nao * nocc * 8);  // C_occ [mu][i]
+    RISP_HIP(hipMemcpy2DAsync(f->co.get(), (size_t)nocc * 8, C.get(), (size_t)nmo * 8, (size_t)nocc * 8, nao,
+                              hipMemcpyDeviceToDevice, s));
+    RISP_HIP(hipStreamSynchronize(s));
     f->ao_partners = std::move(partners);
   }
 }
@@ -1087,29 +1095,27 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
       PhaseScope ps(f->ctx, s, pb + RISP_PHASE_COULOMB_Y,
                     2.0 * mg * ((double)ov * nao + (double)nocc * n2 + (double)nJ * S + 2.0 * nJ * nJ),
                     (double)vsz * mg * ov + 8.0 * ((double)nJ * S + 2.0 * mg * S + mg * n2 + (double)nJ * nJ));
-      // G[m][i][nu] = sum_a X[m][i][a] C_vir[nu][a]
-      Gemm a = g64(nocc, nao, nvir);
-      a.mem_a = tv;
-      a.A = static_cast<const char*>(X) + (size_t)g0 * ov * vsz;
-      a.lda = nvir;
-      a.sa2 = ov;
-      a.B = f->cv_t.get();
-      a.ldb = nao;
-      a.b_kc = false;
+      // G[m][nu][i] = sum_a C_vir[nu][a] X[m][i][a]
+      Gemm a = g64(nao, nocc, nvir);
+      a.A = f->cv_t.get();
+      a.lda = nao;
+      a.a_kc = false;
+      a.mem_b = tv;
+      a.B = static_cast<const char*>(X) + (size_t)g0 * ov * vsz;
+      a.ldb = nvir;
+      a.sb2 = ov;
       a.C = G;
-      a.ldc = nao;
-      a.sc2 = (int64_t)nocc * nao;
+      a.ldc = nocc;
+      a.sc2 = (int64_t)nao * nocc;
       a.nb2 = mg;
       gemm(a, nullptr, s);
-      // D[m][mu][nu] = sum_i C_occ[mu][i] G[m][i][nu]
+      // D[m][mu][nu] = sum_i C_occ[mu][i] G[m][nu][i] (both operands contiguous along i)
       Gemm b = g64(nao, nao, nocc);
-      b.A = f->co_t.get();
-      b.lda = nao;
-      b.a_kc = false;
+      b.A = f->co.get();
+      b.lda = nocc;
       b.B = G;
-      b.ldb = nao;
-      b.b_kc = false;
-      b.sb2 = (int64_t)nocc * nao;
+      b.ldb = nocc;
+      b.sb2 = (int64_t)nao * nocc;
       b.C = D;
       b.ldc = nao;
       b.sc2 = n2;
@@ -1184,13 +1190,14 @@ static void coulomb_ao(risp_factors* f, int m, const void* X, DType tv, void* si
     k_unpack_dense<<<grid_1d((int64_t)mg * S), 256, 0, s>>>(Dp, nao, pk.prow.as<int>(), pk.pcol.as<int>(), S, mg,
                                                             D);
     RISP_LAUNCHED();
-    // H[m][i][nu] = sum_mu C_occ[mu][i] U[m][mu][nu]
+    // H[m][i][nu] = sum_mu C_occ[mu][i] U[m][mu][nu], U read as U[m][nu][mu] (symmetric: both
+    // orientations of a kept pair hold the same integrals and coefficients), so both operands are
+    // contiguous along mu
     Gemm h = g64(nocc, nao, nao);
     h.A = f->co_t.get();
     h.lda = nao;
     h.B = D;
     h.ldb = nao;
-    h.b_kc = false;
     h.sb2 = n2;
     h.C = G;
     h.ldc = nao;

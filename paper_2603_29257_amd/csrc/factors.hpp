@@ -123,10 +123,11 @@ struct risp_factors {
   risp::PairList pairs;
   risp::Operator j_op;
   risp::DevBuf linv_j, co_t, cv_t;  // FP64 L^-1 of the Coulomb metric, C_occ^T [nocc][nao], C_vir^T
+  risp::DevBuf co;                  // C_occ [nao][nocc] (FP64)
   std::vector<int> ao_s0, ao_f0;     // auxiliary shell / function start of each integral chunk (+ end)
   int ao_max_f = 0;                  // functions of the largest chunk
   int ao_mg = 0;                     // trial vectors per group (dense D_m / U_m slices)
-  // workspaces: G / H [ao_mg][nocc][nao], D / U [ao_mg][nao][nao], packed (mu nu|P) chunk [f][S],
+  // workspaces: G [ao_mg][nao][nocc] / H [ao_mg][nocc][nao], D / U [ao_mg][nao][nao], packed (mu nu|P) chunk [f][S],
   // R and L^-1 R
   risp::DevBuf ws_ao_t, ws_ao_d, ws_ao_v, ws_ao_r;
   risp::Partners ao_partners;  // packed layout of the regenerated integrals
