@@ -39,6 +39,9 @@ struct Gemm {
   const float* row_scale = nullptr;
   const float* batch_scale = nullptr;
   int ksplit = 1;  // > 1 splits K over blocks (uses workspace)
+  // A or B is lower triangular (A[i][k] = 0 for k > i, B[j][k] = 0 for k > j): a kernel may skip
+  // those k (the FP64 NT kernel does; the sums keep their order, only exact zero terms are left out)
+  bool a_lower = false, b_lower = false;
   // column split of C: when n_inner > 0, column n is stored at (n / n_inner) * sc_outer + n % n_inner
   // within its row (lets one product write an interleaved [outer][row][inner] layout)
   int n_inner = 0;

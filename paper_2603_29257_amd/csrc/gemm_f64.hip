@@ -66,6 +66,10 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt64(Gemm g, int tiles_m, int ti
     const int tiles = tiles_m * tiles_n;
     const int zb = L / tiles, t = L % tiles;
     grouped_tile(t, tiles_m, tiles_n, tm, tn);
+    // lower-triangular A (B): row (column) tile t costs ~t slices, and each XCD runs a contiguous
+    // range of tiles; alternating light and heavy tiles (0, last, 1, last - 1, ...) evens them out
+    if (g.a_lower) tm = (tm & 1) ? tiles_m - 1 - (tm >> 1) : (tm >> 1);
+    if (g.b_lower) tn = (tn & 1) ? tiles_n - 1 - (tn >> 1) : (tn >> 1);
     split = zb % g.ksplit;
     const int b = zb / g.ksplit;
     const int b1 = b / g.nb2;
@@ -86,6 +90,10 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt64(Gemm g, int tiles_m, int ti
     kbeg = split * kchunk;
     kend = min(K, kbeg + kchunk);
   }
+  // lower-triangular A (B): the tile's rows (columns) end at m0 + BM (n0 + BN), so no later k
+  // contributes
+  if (!GROUPED && g.a_lower) kend = min(kend, m0 + BM);
+  if (!GROUPED && g.b_lower) kend = min(kend, n0 + BN);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 
   const int tid = threadIdx.x;
