@@ -445,7 +445,7 @@ static PartnerPlan partner_plan(const Partners& P, int nl, int nao) {
 
 static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShells& ao, const PairList& pairs,
                                     const Partners& P, const DevShells& aux, const Operator& op, const double* CLT,
-                                    int nl, const double* CRT, int nr, double* out, Arena& ar) {
+                                    int nl, const double* CRT, int nr, double* out, Arena& ar, bool upper) {
   const int nao = ao.nfunc;
   const PartnerPlan pl = partner_plan(P, nl, nao);
   const int max_f = pl.max_f;
@@ -508,18 +508,22 @@ static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShell
       gemm_f64_grouped(g, dd.as<GemmGroup>() + bstart[b], dt.as<int>() + toff[b], bstart[b + 1] - bstart[b], ttot[b],
                        s);
     }
-    // out[P][i][a] = sum_mu G[P][i][mu] CRT[a][mu]
-    Gemm h = g64(nl, nr, nao);
-    h.A = G.get();
-    h.lda = nao;
-    h.sa2 = (int64_t)nl * nao;
-    h.B = CRT;
-    h.ldb = nao;
-    h.C = out + (int64_t)f0 * nl * nr;
-    h.ldc = nr;
-    h.sc2 = (int64_t)nl * nr;
-    h.nb2 = nf;
-    gemm(h, nullptr, s);
+    // out[P][i][a] = sum_mu G[P][i][mu] CRT[a][mu]; upper: the right orbitals start with the left
+    // ones and only a >= i is needed, so each 128-row band starts at its own first row
+    const int band = upper ? 128 : nl;
+    for (int r0 = 0; r0 < nl; r0 += band) {
+      Gemm h = g64(std::min(band, nl - r0), nr - (upper ? r0 : 0), nao);
+      h.A = G.as<double>() + (size_t)r0 * nao;
+      h.lda = nao;
+      h.sa2 = (int64_t)nl * nao;
+      h.B = CRT + (upper ? (size_t)r0 * nao : 0);
+      h.ldb = nao;
+      h.C = out + (int64_t)f0 * nl * nr + (int64_t)r0 * nr + (upper ? r0 : 0);
+      h.ldc = nr;
+      h.sc2 = (int64_t)nl * nr;
+      h.nb2 = nf;
+      gemm(h, nullptr, s);
+    }
     f0 += nf;
     s0 = s1;
   }
@@ -639,9 +643,11 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
   const bool sparse_t = prm->dense_transform == 0;
   if (sparse_t || prm->j_mode == RISP_J_AO_DIRECT) build_partners(sys, pairs, partners, s);
   Arena ar;
+  // upper: CRT starts with the nl orbitals of CLT and only out[P][i][a] with a >= i is needed (the
+  // partner path skips most of the rest; the dense path computes everything)
   auto t3c = [&](const DevShells& aux, const Operator& op, const double* CLT, int nl, const double* CRT, int nr,
-                 double* out) {
-    if (sparse_t) transformed_3c_partners(ctx, s, ao, pairs, partners, aux, op, CLT, nl, CRT, nr, out, ar);
+                 double* out, bool upper = false) {
+    if (sparse_t) transformed_3c_partners(ctx, s, ao, pairs, partners, aux, op, CLT, nl, CRT, nr, out, ar, upper);
     else transformed_3c(ctx, s, ao, pairs, aux, op, CLT, nl, CRT, nr, out);
   };
   // arena bytes of one t3c call with nl left orbitals (the dense path allocates its own buffers)
@@ -879,23 +885,27 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
       const size_t mk = ar.mark();
       const WsView Tab = ar.take((size_t)nks * na * nvk * 8);
       const WsView tmp = ar.take(metric_panel_bytes(nks, (int64_t)na * nvk));
+      // T^P_ab is symmetric in (a, b): a chunk of rows a0 <= a < a0 + nac forms the columns b >= a0
+      // only (its transform skips most b < a), stores what it formed with b >= a0, and the strict
+      // lower triangle is mirrored from the upper one once every chunk is stored
       for (int a0 = 0; a0 < nvk; a0 += na) {
-        const int nac = std::min(na, nvk - a0);
-        const int64_t cols = (int64_t)nac * nvk;
-        t3c(ak, blocks[blk], CvKT.as<double>() + (size_t)a0 * nao, nac, CvKT.as<double>(), nvk, Tab.as<double>());
+        const int nac = std::min(na, nvk - a0), nb = nvk - a0;
+        const int64_t cols = (int64_t)nac * nb;
+        const double* Ca = CvKT.as<double>() + (size_t)a0 * nao;
+        t3c(ak, blocks[blk], Ca, nac, Ca, nb, Tab.as<double>(), true);
         metric_apply_inplace(Linv.as<double>(), nks, Tab.as<double>(), cols, tmp, s);
-        // chunk element (p, a, a0 + a) is Bx^P_aa of window virtual a0 + a
-        gather_strided(Tab.as<double>() + a0, nks, nac, (int64_t)nac * nvk, nvk + 1,
-                       Baa.as<double>() + (size_t)blk * nks * nvk + a0, nvk, s);
-        if (bf) row_absmax(Tab.as<double>(), nks, cols, cols, mxab.as<double>() + blk * nks, a0 > 0, s);
-        // rows (p, a) of the chunk -> stored rows (blk * nks + p) * nvk + a0 + a
-        const size_t r0 = ((size_t)blk * nks * nvk + a0) * f->nvkp;
+        // chunk element (p, a, a) is Bx^P_aa of window virtual a0 + a
+        gather_strided(Tab.as<double>(), nks, nac, cols, nb + 1, Baa.as<double>() + (size_t)blk * nks * nvk + a0, nvk,
+                       s);
+        if (bf) row_absmax_upper(Tab.as<double>(), nks, nac, nb, mxab.as<double>() + blk * nks, a0 > 0, s);
+        // chunk element (p, a, b) -> stored row (blk * nks + p) * nvk + a0 + a, column a0 + b
+        const size_t r0 = ((size_t)blk * nks * nvk + a0) * f->nvkp + a0;
         if (bf)
-          store_block_split(Tab.as<double>(), nvk, nac, f->t_ab.as<uint16_t>() + r0, f->t_ab_lo.as<uint16_t>() + r0,
-                            f->nvkp, nvk, nks, nac, nvk, s);
+          store_block_split(Tab.as<double>(), nb, nac, f->t_ab.as<uint16_t>() + r0, f->t_ab_lo.as<uint16_t>() + r0,
+                            f->nvkp, nvk, nks, nac, nb, s);
         else
-          store_block(Tab.get(), DType::F64, nvk, nac, static_cast<char*>(f->t_ab.get()) + r0 * dsz, tdst, f->nvkp,
-                      nvk, nks, nac, nvk, s);
+          store_block(Tab.get(), DType::F64, nb, nac, static_cast<char*>(f->t_ab.get()) + r0 * dsz, tdst, f->nvkp,
+                      nvk, nks, nac, nb, s);
       }
       RISP_HIP(hipStreamSynchronize(s));
       ar.release_to(mk);
@@ -918,6 +928,9 @@ void build_factors(risp_ctx* ctx, const risp_system* sys, const risp_params* prm
                          f->diag64.as<double>(), s);
       RISP_HIP(hipStreamSynchronize(s));
     }
+    // the strict lower triangle of every T^P_ab from its upper triangle (BF16: both staged halves)
+    mirror_lower(f->t_ab.get(), bf ? 2 : (int)dsz, nK, nvk, f->nvkp, (int64_t)nvk * f->nvkp, s);
+    if (bf) mirror_lower(f->t_ab_lo.get(), 2, nK, nvk, f->nvkp, (int64_t)nvk * f->nvkp, s);
     DevBuf sij, sab;
     if (bf) {
       slice_scales(Bij.as<double>(), nK, (int64_t)nok * nok, prm->bf16_scale != 0, sij, s);

@@ -265,6 +265,61 @@ __global__ __launch_bounds__(256) void k_row_absmax(const double* __restrict__ A
   if (threadIdx.x == 0) out[blockIdx.x] = acc ? fmax(out[blockIdx.x], red[0]) : red[0];
 }
 
+// out[p] = max(out[p] (if acc), max |A[p][i][j]| over j >= i) for A [np][nr][nc], one block per p
+__global__ __launch_bounds__(256) void k_row_absmax_upper(const double* __restrict__ A, int nr, int nc,
+                                                          double* __restrict__ out, int acc) {
+  __shared__ double red[256];
+  const int64_t n = (int64_t)nr * nc;
+  const double* a = A + (int64_t)blockIdx.x * n;
+  double m = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += blockDim.x)
+    if (t % nc >= t / nc) m = fmax(m, fabs(a[t]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < d) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = acc ? fmax(out[blockIdx.x], red[0]) : red[0];
+}
+
+void row_absmax_upper(const double* A, int np, int nr, int nc, double* out, bool accumulate, hipStream_t s) {
+  if (np == 0 || (int64_t)nr * nc == 0) return;
+  k_row_absmax_upper<<<np, 256, 0, s>>>(A, nr, nc, out, accumulate ? 1 : 0);
+  RISP_LAUNCHED();
+}
+
+// X[p][r][c] = X[p][c][r] for c < r < n (row stride ld, slice stride sp): the strict lower triangle
+// of each slice from its upper triangle, through 32 x 32 tiles in LDS. Block (bx, by, p) writes the
+// tile of rows by and columns bx (bx <= by) from the mirrored tile of rows bx and columns by.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mirror_lower(T* __restrict__ X, int n, int64_t ld, int64_t sp) {
+  const int bx = blockIdx.x, by = blockIdx.y;
+  if (bx > by) return;
+  T* S = X + (int64_t)blockIdx.z * sp;
+  __shared__ T tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int row = bx * 32 + r, col = by * 32 + tx;
+    if (row < n && col < n) tile[r][tx] = S[(int64_t)row * ld + col];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int row = by * 32 + r, col = bx * 32 + tx;
+    if (row < n && col < row) S[(int64_t)row * ld + col] = tile[tx][r];
+  }
+}
+
+void mirror_lower(void* X, int esz, int np, int n, int64_t ld, int64_t sp, hipStream_t s) {
+  if (np == 0 || n <= 1) return;
+  RISP_CHECK(np <= 65535, RISP_E_SHAPE, "mirror_lower: too many slices");
+  const dim3 grid(ceil_div(n, 32), ceil_div(n, 32), np);
+  if (esz == 2) k_mirror_lower<uint16_t><<<grid, 256, 0, s>>>(static_cast<uint16_t*>(X), n, ld, sp);
+  else if (esz == 4) k_mirror_lower<float><<<grid, 256, 0, s>>>(static_cast<float*>(X), n, ld, sp);
+  else k_mirror_lower<double><<<grid, 256, 0, s>>>(static_cast<double*>(X), n, ld, sp);
+  RISP_LAUNCHED();
+}
+
 void row_absmax(const double* A, int rows, int64_t cols, int64_t lda, double* out, bool accumulate, hipStream_t s) {
   if (rows == 0) return;
   k_row_absmax<<<rows, 256, 0, s>>>(A, cols, lda, out, accumulate ? 1 : 0);

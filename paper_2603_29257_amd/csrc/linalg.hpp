@@ -35,6 +35,11 @@ inline int64_t pad8(int64_t n) { return (n + 7) / 8 * 8; }
 
 // out[r] = max_c |A[r * lda + c]| over c < cols (max with the previous out[r] when accumulate)
 void row_absmax(const double* A, int rows, int64_t cols, int64_t lda, double* out, bool accumulate, hipStream_t s);
+// out[p] = max(out[p] (if accumulate), max |A[p][i][j]| over j >= i) for A [np][nr][nc]
+void row_absmax_upper(const double* A, int np, int nr, int nc, double* out, bool accumulate, hipStream_t s);
+// X[p][r][c] = X[p][c][r] for c < r < n in each of np slices (element size esz = 2, 4 or 8 bytes,
+// row stride ld, slice stride sp elements)
+void mirror_lower(void* X, int esz, int np, int n, int64_t ld, int64_t sp, hipStream_t s);
 
 // scale[r] = smallest power of two >= mx[r] (1 where mx[r] = 0, or everywhere when not enabled)
 void pow2_from_max(const double* mx, int n, bool enabled, float* scale, hipStream_t s);
