@@ -447,6 +447,7 @@ static void transformed_3c_partners(risp_ctx* ctx, hipStream_t s, const DevShell
                                     const Partners& P, const DevShells& aux, const Operator& op, const double* CLT,
                                     int nl, const double* CRT, int nr, double* out, Arena& ar, bool upper) {
   const int nao = ao.nfunc;
+  RISP_CHECK(!upper || nr >= nl, RISP_E_STATE, "upper transform: the right orbitals must include the left ones");
   const PartnerPlan pl = partner_plan(P, nl, nao);
   const int max_f = pl.max_f;
   const std::vector<int>& bstart = pl.bstart;

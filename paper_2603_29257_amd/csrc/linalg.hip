@@ -311,13 +311,17 @@ __global__ __launch_bounds__(256) void k_mirror_lower(T* __restrict__ X, int n, 
 }
 
 void mirror_lower(void* X, int esz, int np, int n, int64_t ld, int64_t sp, hipStream_t s) {
-  if (np == 0 || n <= 1) return;
-  RISP_CHECK(np <= 65535, RISP_E_SHAPE, "mirror_lower: too many slices");
-  const dim3 grid(ceil_div(n, 32), ceil_div(n, 32), np);
-  if (esz == 2) k_mirror_lower<uint16_t><<<grid, 256, 0, s>>>(static_cast<uint16_t*>(X), n, ld, sp);
-  else if (esz == 4) k_mirror_lower<float><<<grid, 256, 0, s>>>(static_cast<float*>(X), n, ld, sp);
-  else k_mirror_lower<double><<<grid, 256, 0, s>>>(static_cast<double*>(X), n, ld, sp);
-  RISP_LAUNCHED();
+  if (np <= 0 || n <= 1) return;
+  RISP_CHECK(esz == 2 || esz == 4 || esz == 8, RISP_E_ARG, "mirror_lower: element size must be 2, 4 or 8 bytes");
+  RISP_CHECK(ceil_div(n, 32) <= 65535, RISP_E_SHAPE, "mirror_lower: slices too large");
+  for (int p0 = 0; p0 < np; p0 += 65535) {  // at most 65535 slices per launch (grid z)
+    const dim3 grid(ceil_div(n, 32), ceil_div(n, 32), std::min(np - p0, 65535));
+    char* Xp = static_cast<char*>(X) + (size_t)p0 * sp * esz;
+    if (esz == 2) k_mirror_lower<uint16_t><<<grid, 256, 0, s>>>(reinterpret_cast<uint16_t*>(Xp), n, ld, sp);
+    else if (esz == 4) k_mirror_lower<float><<<grid, 256, 0, s>>>(reinterpret_cast<float*>(Xp), n, ld, sp);
+    else k_mirror_lower<double><<<grid, 256, 0, s>>>(reinterpret_cast<double*>(Xp), n, ld, sp);
+    RISP_LAUNCHED();
+  }
 }
 
 void row_absmax(const double* A, int rows, int64_t cols, int64_t lda, double* out, bool accumulate, hipStream_t s) {

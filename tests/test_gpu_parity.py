@@ -235,6 +235,21 @@ def test_factors_chunked_build_identical(ctx, mol0, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_t_ab_slices_exactly_symmetric(ctx, mol0, prec):
+    # T^P_ab is symmetric in (a, b): the build forms the upper triangle and mirrors the strict lower
+    # one, so every stored slice (BF16: both halves) equals its transpose bit for bit, whether the
+    # window virtuals are transformed in one chunk or one orbital at a time
+    import paper_2603_29257_amd as P
+    for kib in (0, 16):
+        F = _gpu_factors(ctx, mol0, precision=P.PRECISIONS[prec], build_chunk_kib=kib)
+        for name in ("t_ab", "t_ab_lo") if prec == "bf16" else ("t_ab",):
+            t = F.tensor(name).double().cpu().numpy()
+            assert t.shape[1] == t.shape[2] == F.nvir_k and t.shape[1] > 1
+            assert np.array_equal(t, np.swapaxes(t, 1, 2)), (name, kib)
+        F.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("m", [1, 7, 30])
 def test_sigma_matches_oracle(ctx, mol0, oracle0, prec, m):
     import paper_2603_29257_amd as P
