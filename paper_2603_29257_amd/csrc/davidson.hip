@@ -562,7 +562,6 @@ void DavidsonRun::store_T(int r0, int n) {
 // Called after the requested sigma rows are in W. Advances to the next request or finishes.
 void DavidsonRun::complete() {
   Timer tsub;
-  const int64_t ov = ov_;
   res_.sigma_vectors += rq_.n;
   res_.sigma_flops += sigma_flops(f_, rq_.n);
   if (state_ == State::Init) {
