@@ -36,9 +36,17 @@ __global__ __launch_bounds__(NT, 1) void k_gemm_nt64(Gemm g, int tiles_m, int ti
   constexpr int FM = BM / 2 / 16, FN = WN / 16;
   __shared__ __attribute__((aligned(16))) char lds[2 * STAGE];
 
+  // runs of 32 consecutive tiles (one XCD's resident blocks) dealt to the XCDs in turn: hardware
+  // block w runs on XCD w % 8 as its (w / 8)-th block; a last partial round keeps the hardware order
+  // (1000-atom build: 13.58 -> 13.14 s against one contiguous range of tiles per XCD)
+  constexpr int SEG = 32;
   const int W = gridDim.x, w = blockIdx.x;
-  const int per = (W + 7) / 8, tall = (W % 8 == 0) ? 8 : W % 8, x = w % 8, qb8 = w / 8;
-  const int L = x < tall ? x * per + qb8 : tall * per + (x - tall) * (per - 1) + qb8;
+  const int full = W / (8 * SEG) * (8 * SEG);
+  int L = w;
+  if (w < full) {
+    const int x = w % 8, qb8 = w / 8;
+    L = ((qb8 / SEG) * 8 + x) * SEG + qb8 % SEG;
+  }
   int tm, tn, split = 0, b2 = 0, K, N, n_inner = g.n_inner;
   int64_t lda, ldb, zoff = 0;
   const double* A;
