@@ -72,6 +72,16 @@ def test_dense_A_matches_brute_force(tiny, window):
         assert len(F.virK) < F.nvir
 
 
+def test_exchange_factor_slices_symmetric(tiny):
+    # (pq|P) is symmetric in (p, q), and the metric split acts on P only, so every slice of the
+    # windowed exchange factors is symmetric; the GPU build relies on it for T_ab (it forms the
+    # upper triangle and mirrors it)
+    F = R.build_factors(tiny, R.Params())
+    for B in (F.Bx_ab, F.Bx_ij):
+        assert B.shape[0] > 0 and B.shape[1] > 1
+        assert np.abs(B - np.swapaxes(B, 1, 2)).max() <= 1e-13 * np.abs(B).max()
+
+
 def test_A_symmetric_and_coulomb_psd(tiny):
     F = R.build_factors(tiny, R.Params(schwarz_tau=0.0))
     A = R.dense_A(F)
