@@ -275,8 +275,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding over the auxiliary "
-                                   "index is a design note, not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; multi-GPU sharding over the "
+                                   "auxiliary index is a design note, not an implemented path", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch

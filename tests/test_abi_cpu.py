@@ -88,3 +88,16 @@ def test_job_footprint_host_model():
         bad = synth.make_chain_ring(40, 40)
         bad.nocc = 0
         abi.job_footprint(abi.System(bad), abi.Params(), nstates=5)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: --gpus N > 1 exits with status 2 and a JSON line saying so, before touching a GPU
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
